@@ -1,0 +1,201 @@
+"""CPU oracle for brute-force incoherent de-dispersion.
+
+TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
+CPU-baseline leg of `bench.py` may import this package.  It shares no code
+with the HIP library (`paper_1107_2516_amd`): the delay arithmetic, the
+half-precision decoding and the channel sum are written again here, from the
+paper, in plain C (dd_oracle.c) and Python.
+
+What it computes (paper section and equation cited at each function):
+
+* `delay_table`     per-(DM, channel) integer shifts, FP64, section 3 "Shifts".
+* `dedisperse`      out[d][t] = sum_c in[c][t + delay[d][c]], section 3.1,
+                    FP64 accumulation (f32/f16/f64 inputs) or int64 (u8).
+* `snr`, `detect`   buffer statistics and an n-sigma threshold emitting
+                    (time, DM, intensity) triplets, section 3 (output thread).
+* `paper_maxshift`  the first-order maximum-shift bound of section 3
+                    ("Maximum shift" equation), used only as a sanity bound.
+
+Pins: every function is checked in `tests/test_oracle_*.py` against values
+the paper or the mathematics fix (exact rationals, closed forms, special
+cases, invariants, the paper's worked example).  None is "parity unpinned".
+"""
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+from . import exact  # noqa: F401  (re-export)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+ORC_OK, ORC_EINVAL, ORC_ERANGE = 0, -1, -3
+
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_ptr = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        src = os.path.join(_HERE, "dd_oracle.c")
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+            from .build import build
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.orc_delays.argtypes = [_i32, _dbl, _dbl, _dbl, _ptr, _i32, _ptr]
+        lib.orc_delays.restype = ctypes.c_int
+        for name in ("orc_dedisperse_f32", "orc_dedisperse_f64", "orc_dedisperse_f16",
+                     "orc_dedisperse_u8"):
+            fn = getattr(lib, name)
+            fn.argtypes = [_ptr, _i64, _i64, _i64, _ptr, _i32, _ptr, _i32, _i64, _i64, _ptr, _i32]
+            fn.restype = ctypes.c_int
+        lib.orc_half_to_double.argtypes = [ctypes.c_uint16]
+        lib.orc_half_to_double.restype = _dbl
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+class OracleError(ValueError):
+    pass
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def channel_freqs(nchans: int, f_top: float, df: float) -> np.ndarray:
+    """f_c = f_top - c*df, channel 0 at the top (section 4, Table 2 parameters)."""
+    return np.array([f_top - c * df for c in range(nchans)], dtype=np.float64)
+
+
+def delay_table(nchans: int, f_top: float, df: float, t_samp: float, dms) -> np.ndarray:
+    """Integer shifts [ndms, nchans] in samples (section 3, "Shifts").
+
+    t_chan = 4150 (f_c^-2 - f_top^-2) seconds per unit DM, then
+    t_DM = t_chan * DM / t_samp, rounded half away from zero; FP64 throughout.
+    """
+    dms = np.ascontiguousarray(np.asarray(dms, dtype=np.float64).reshape(-1))
+    out = np.empty((dms.size, nchans), dtype=np.int64)
+    rc = _load().orc_delays(int(nchans), float(f_top), float(df), float(t_samp),
+                            dms.ctypes.data, int(dms.size), out.ctypes.data)
+    if rc != ORC_OK:
+        raise OracleError(f"invalid plan arguments (rc={rc})")
+    return out
+
+
+def max_shift(delays: np.ndarray) -> int:
+    """Largest shift of the table: the extra samples every DM row needs (section 3)."""
+    return int(np.max(delays))
+
+
+def half_to_double(h: int) -> float:
+    return float(_load().orc_half_to_double(int(h)))
+
+
+def dedisperse(data: np.ndarray, delays: np.ndarray, rows=None, t_begin: int = 0,
+               t_end=None, nthreads: int = 0) -> np.ndarray:
+    """Brute-force de-dispersion (section 3.1).
+
+    data   [nchans, nsamp] channel-major, time contiguous; float32, float16,
+           float64 or uint8.  Rows may be padded (row stride >= nsamp).
+    delays [ndms, nchans] integer shifts.
+    rows   DM row indices to compute (default: all).
+    Returns float64 [len(rows), t_end - t_begin] for float inputs and int64
+    for uint8, summed over channels in order 0..nchans-1.
+    Default t_end is nout = nsamp - max_shift(delays).
+    """
+    if data.ndim != 2:
+        raise OracleError("data must be 2-D [nchans, nsamp]")
+    nchans, nsamp = data.shape
+    if data.strides[1] != data.itemsize or data.strides[0] % data.itemsize:
+        raise OracleError("time axis must be contiguous")
+    stride = data.strides[0] // data.itemsize
+    delays = np.ascontiguousarray(delays, dtype=np.int64)
+    if delays.ndim != 2 or delays.shape[1] != nchans:
+        raise OracleError("delays must be [ndms, nchans]")
+    ndms = delays.shape[0]
+    if rows is None:
+        rows = np.arange(ndms, dtype=np.int32)
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1))
+    if t_end is None:
+        t_end = nsamp - max_shift(delays)
+    n = int(t_end) - int(t_begin)
+    if n < 0:
+        raise OracleError("empty or negative time range")
+    lib = _load()
+    if data.dtype == np.float32:
+        fn, acc = lib.orc_dedisperse_f32, np.float64
+    elif data.dtype == np.float64:
+        fn, acc = lib.orc_dedisperse_f64, np.float64
+    elif data.dtype == np.float16:
+        fn, acc = lib.orc_dedisperse_f16, np.float64
+    elif data.dtype == np.uint8:
+        fn, acc = lib.orc_dedisperse_u8, np.int64
+    else:
+        raise OracleError(f"unsupported dtype {data.dtype}")
+    out = np.empty((rows.size, max(n, 0)), dtype=acc)
+    rc = fn(data.ctypes.data, nchans, nsamp, stride, delays.ctypes.data, ndms,
+            rows.ctypes.data, rows.size, int(t_begin), int(t_end), out.ctypes.data, int(nthreads))
+    if rc == ORC_ERANGE:
+        raise OracleError("requested time range reads past the end of the input")
+    if rc != ORC_OK:
+        raise OracleError(f"invalid arguments (rc={rc})")
+    return out
+
+
+def paper_maxshift(f: float, bandwidth: float, dm_max: float, t_samp: float) -> float:
+    """First-order maximum shift of section 3 ("Maximum shift" equation):
+    m_shift = 8.3e6 ms * delta_f * f^-3 * DM_max / t_samp, with t_samp in ms.
+    Here t_samp is in seconds, so the constant becomes 8300 s."""
+    return 8300.0 * bandwidth * f ** -3 * dm_max / t_samp
+
+
+def row_stats(out: np.ndarray, robust: bool = True):
+    """Per-row baseline and scale of a de-dispersed buffer.
+
+    robust=False gives the mean and standard deviation that section 3 applies
+    to the processed buffer; robust=True gives the median and 1.4826*MAD,
+    which a bright injected pulse does not inflate.
+    """
+    x = np.asarray(out, dtype=np.float64)
+    if robust:
+        mu = np.median(x, axis=-1)
+        sigma = 1.482602218505602 * np.median(np.abs(x - mu[..., None]), axis=-1)
+    else:
+        mu = x.mean(axis=-1)
+        sigma = x.std(axis=-1)
+    return mu, sigma
+
+
+def snr(out: np.ndarray, width: int = 1, robust: bool = True) -> np.ndarray:
+    """Boxcar S/N of every window of `width` samples in each row:
+    (sum of the window - width*mu) / (sigma*sqrt(width))."""
+    x = np.asarray(out, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[None, :]
+    mu, sigma = row_stats(x, robust)
+    c = np.cumsum(np.pad(x, ((0, 0), (1, 0))), axis=-1)
+    box = c[:, width:] - c[:, :-width]
+    return (box - width * mu[:, None]) / (sigma[:, None] * np.sqrt(width))
+
+
+def detect(out: np.ndarray, nsigma: float, dms=None):
+    """Threshold of section 3's output thread: mean and standard deviation of
+    the whole processed buffer, then every value above mu + nsigma*sigma is
+    reported as a (time, DM, intensity) triplet, in row-major order."""
+    x = np.asarray(out, dtype=np.float64)
+    mu, sigma = x.mean(), x.std()
+    d_idx, t_idx = np.nonzero(x > mu + nsigma * sigma)
+    dmv = d_idx if dms is None else np.asarray(dms)[d_idx]
+    return list(zip(t_idx.tolist(), np.asarray(dmv).tolist(), x[d_idx, t_idx].tolist()))
