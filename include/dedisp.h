@@ -1,0 +1,252 @@
+/*
+ * libdedisp — brute-force incoherent de-dispersion for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Magro et al., "Real-time, fast radio transient searches with GPU
+ * de-dispersion" (MNRAS 2011, arXiv 1107.2516).  For every trial DM d and
+ * frequency channel c an integer shift delay[d][c] follows from the cold-plasma
+ * dispersion law (section 1, dispersion-law equation) split as in section 3
+ * ("Shifts"):
+ *     t_chan[c]   = 4150 s * (f_c^-2 - f_top^-2)          (f in MHz)
+ *     delay[d][c] = round(t_chan[c] * DM_d / t_samp)        (ties away from 0)
+ * evaluated on the host in FP64.  De-dispersion (section 3.1) then sums the
+ * shifted channels:
+ *     out[d][t] = sum over c of in[c][t + delay[d][c]],   0 <= t < nout,
+ * with nout = nsamp - max_shift and max_shift the largest table entry, the
+ * "maximum shift" extra samples of section 3.
+ *
+ * Conventions used by every call:
+ *  - Channel c has frequency f_c = f_top - c*df (channel 0 at the top, df > 0).
+ *  - Frequencies in MHz, times in seconds, DMs in pc cm^-3.
+ *  - Filterbank input is channel-major with time contiguous ("channel order",
+ *    section 3.1): sample (c, t) is at in[c*in_stride + t], in_stride >= nsamp.
+ *  - Output row d (in the caller's DM order) is at out[d*out_stride + t],
+ *    out_stride >= nout.
+ *  - Supported (input, output) type pairs: (DD_F32, DD_F32), (DD_F16, DD_F32)
+ *    with FP32 accumulation, and (DD_U8, DD_I32) with exact integer sums.
+ *  - Device pointers are HIP device memory (for example the data pointer of a
+ *    torch tensor on a ROCm device); the caller owns them.  `stream` is a
+ *    hipStream_t (NULL = the default stream).  Calls that take a stream only
+ *    enqueue work and return; errors found while enqueueing are returned,
+ *    faults during execution surface at the next synchronisation.
+ *  - Every entry point returns a dd_status; none aborts, and no C++ exception
+ *    crosses this interface.  dd_last_error() returns a thread-local message
+ *    describing the last failure on the calling thread.
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dd_status {
+  DD_OK = 0,
+  DD_ERR_INVALID_ARG = -1,    /* bad sizes, strides, frequencies, DMs, NULL pointers */
+  DD_ERR_DTYPE = -2,          /* unsupported (input, output) type pair */
+  DD_ERR_NSAMP = -3,          /* nsamp <= max_shift: no complete output sample */
+  DD_ERR_OOM = -4,            /* host or device allocation failed */
+  DD_ERR_HIP = -5,            /* a HIP runtime call failed (message in dd_last_error) */
+  DD_ERR_AGAIN = -6,          /* serving queue full: retry after polling */
+  DD_ERR_TOO_LARGE = -7,      /* request larger than the configured budget or limit */
+  DD_ERR_NOT_FOUND = -8,      /* unknown beam or ticket */
+  DD_ERR_NOT_IMPLEMENTED = -9,
+  DD_ERR_STATE = -10          /* call not valid in the object's current state */
+} dd_status;
+
+typedef enum dd_dtype { DD_U8 = 1, DD_F16 = 2, DD_F32 = 3, DD_I32 = 4 } dd_dtype;
+
+typedef struct dd_plan dd_plan;
+
+/* ------------------------------------------------------------------------ */
+/* Plans                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Build a plan: the FP64 delay table of section 3 ("Shifts") for `ndms` trial
+ * DMs (any order, duplicates allowed) and `nchans` channels.
+ *   nchans >= 1, df_mhz > 0, f_top_mhz - (nchans-1)*df_mhz > 0, t_samp_s > 0,
+ *   every DM finite and >= 0, ndms >= 1, nchans <= 2^23 (int32 sums of 8-bit
+ *   data stay exact).  Otherwise DD_ERR_INVALID_ARG and *out untouched.
+ * The plan owns a host copy of the table; its device copy is uploaded lazily,
+ * once per device, on first use.  A plan is immutable after creation and may
+ * be used from several threads and streams at once.  No GPU work happens here.
+ */
+dd_status dd_plan_create(int32_t nchans, double f_top_mhz, double df_mhz, double t_samp_s,
+                         const double* dm_list, int32_t ndms, dd_plan** out);
+
+/*
+ * Build a plan from an explicit host table delays[d*nchans + c] (row-major
+ * [ndms][nchans], every entry >= 0).  Lets tests drive the kernels with
+ * arbitrary shifts.  DD_ERR_INVALID_ARG for negative entries or bad sizes.
+ */
+dd_status dd_plan_create_from_delays(int32_t nchans, int32_t ndms, const int32_t* delays,
+                                     dd_plan** out);
+
+/* Sizes of a plan; any output pointer may be NULL. */
+dd_status dd_plan_info(const dd_plan* plan, int32_t* nchans, int32_t* ndms, int32_t* max_shift);
+
+/* Copy the plan's table to host memory host_out[d*nchans + c] (ndms*nchans int32). */
+dd_status dd_delay_table(const dd_plan* plan, int32_t* host_out);
+
+/* Release a plan (NULL is accepted).  The caller must make sure no enqueued
+ * work still uses it. */
+dd_status dd_plan_destroy(dd_plan* plan);
+
+/* ------------------------------------------------------------------------ */
+/* De-dispersion (section 3.1)                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Enqueue out[d][t] = sum_c in[c][t + delay[d][c]] for all d < ndms and
+ * t < nout = nsamp - max_shift on `stream`.
+ *   d_in  device, in_t elements, nchans rows of in_stride (>= nsamp) elements.
+ *   d_out device, out_t elements, ndms rows of out_stride (>= nout) elements;
+ *         elements t >= nout of each row are not written.
+ * Errors: DD_ERR_INVALID_ARG (NULL pointers, strides), DD_ERR_DTYPE (type
+ * pair), DD_ERR_NSAMP (nsamp <= max_shift), DD_ERR_HIP (launch failure).
+ * FP32 results are summed in FP32 in channel blocks (see DESIGN notes in the
+ * repository); 8-bit results are exact.
+ */
+dd_status dd_execute(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
+                     int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
+                     void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many beams, one persistent launch                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dd_batch dd_batch;
+
+typedef struct dd_batch_item {
+  const dd_plan* plan;  /* borrowed; must outlive the batch */
+  const void* d_in;     /* device input of this beam */
+  int64_t nsamp;        /* samples per channel (> plan max_shift) */
+  int64_t in_stride;    /* elements between channel rows (>= nsamp) */
+  void* d_out;          /* device output of this beam */
+  int64_t out_stride;   /* elements between DM rows (>= nsamp - max_shift) */
+} dd_batch_item;
+
+/*
+ * Describe `n` beams that share (in_t, out_t) and are processed together by
+ * one persistent kernel: every (beam, DM tile, time tile) work item is pulled
+ * from a device queue by a fixed grid sized to the GPU.  Tile shapes come from
+ * the autotune cache (dd_autotune) or the built-in defaults.  The launch is
+ * recorded into a HIP graph on first use and replayed afterwards.
+ */
+dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, dd_dtype out_t,
+                          dd_batch** out);
+
+/* Point the batch at new buffers of the same shapes (same plans, nsamp and
+ * strides, same n); the captured graph is kept.  DD_ERR_INVALID_ARG if any
+ * shape differs. */
+dd_status dd_batch_update(dd_batch* batch, const dd_batch_item* items, int32_t n);
+
+/* Enqueue the whole batch on `stream` (graph replay). */
+dd_status dd_batch_launch(dd_batch* batch, void* stream);
+
+dd_status dd_batch_destroy(dd_batch* batch);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuning                                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dd_tile_config {
+  int32_t variant;      /* kernel variant index (implementation-defined) */
+  int32_t dms_per_wave; /* DM trials per wavefront */
+  int32_t waves;        /* wavefronts per workgroup */
+  int32_t tsamp_per_lane; /* output samples per lane */
+  int32_t chans_per_stage; /* channels staged in LDS per pipeline step */
+} dd_tile_config;
+
+/*
+ * Time the candidate tile shapes for (plan, in_t, nsamp) on `stream` using
+ * scratch buffers it allocates and frees, keep the fastest in the process-wide
+ * cache (and in the file named by DD_TUNE_CACHE, if set), and return it.
+ * Blocks until the timing is done.  best_ms may be NULL.
+ */
+dd_status dd_autotune(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, void* stream,
+                      dd_tile_config* best, float* best_ms);
+
+/* The tile shape dd_execute would use now for (plan, in_t, nsamp). */
+dd_status dd_tile_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, dd_tile_config* cfg);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of streaming chunks from many beams          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dd_server dd_server;
+
+typedef struct dd_serve_config {
+  dd_dtype in_t;           /* input sample type of every beam */
+  dd_dtype out_t;          /* output type (pair rules as dd_execute) */
+  int32_t max_inflight;    /* chunks on the device at once (>= 1) */
+  int32_t queue_capacity;  /* host submit queue length (>= 1) */
+  int32_t nstreams;        /* HIP streams used to overlap chunks (>= 1) */
+} dd_serve_config;
+
+typedef struct dd_result {
+  uint64_t ticket;
+  int32_t beam;
+  int32_t status;          /* dd_status of this chunk */
+  int64_t seq;             /* caller's sequence number */
+  int64_t t_first;         /* absolute output sample of row element 0 */
+  int64_t nout;            /* output samples per DM row (0 while warming up) */
+  void* d_out;             /* device output, ndms rows of out_stride elements */
+  int64_t out_stride;
+  double t_submit, t_admit, t_done; /* seconds, steady clock of this process */
+} dd_result;
+
+/*
+ * Create a server that sub-allocates all of its device memory (per-beam
+ * overlap carries, chunk staging, outputs) from the caller's arena
+ * [d_arena, d_arena + arena_bytes).  A chunk is admitted only when the arena
+ * has room for it (the memory rule of section 3, "Processable Samples").
+ */
+dd_status dd_serve_create(const dd_serve_config* cfg, void* d_arena, size_t arena_bytes,
+                          dd_server** out);
+
+/*
+ * Register a beam that streams data for `plan`, in chunks of at most
+ * max_chunk samples.  Reserves the beam's carry: the last max_shift samples
+ * of every channel stay on the device between chunks (section 3, "Maximum
+ * shift").  DD_ERR_TOO_LARGE if the carry does not fit the arena.
+ */
+dd_status dd_serve_add_beam(dd_server* srv, const dd_plan* plan, int64_t max_chunk, int32_t* beam);
+
+/*
+ * Queue one chunk: nsamp samples of every channel, host memory laid out
+ * [nchans][nsamp] (pinned memory is copied asynchronously).  The chunk is
+ * copied before this call returns.  seq must increase by one per beam;
+ * a gap restarts the beam (its carry is dropped and it warms up again).
+ * DD_ERR_AGAIN when the queue is full, DD_ERR_TOO_LARGE when nsamp exceeds
+ * the beam's max_chunk.
+ */
+dd_status dd_serve_submit(dd_server* srv, int32_t beam, const void* h_chunk, int64_t nsamp,
+                          int64_t seq, uint64_t* ticket);
+
+/* Collect up to `max` finished chunks (non-blocking). */
+dd_status dd_serve_poll(dd_server* srv, dd_result* out, int32_t max, int32_t* n);
+
+/* Return a finished chunk's output memory to the arena. */
+dd_status dd_serve_release(dd_server* srv, uint64_t ticket);
+
+/* Wait until every queued chunk has finished (results stay pollable). */
+dd_status dd_serve_drain(dd_server* srv);
+
+dd_status dd_serve_destroy(dd_server* srv);
+
+/* ------------------------------------------------------------------------ */
+
+const char* dd_status_str(dd_status s);
+const char* dd_last_error(void);
+/* Library version, "major.minor.patch". */
+const char* dd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEDISP_H */

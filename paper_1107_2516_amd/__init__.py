@@ -1,0 +1,263 @@
+"""libdedisp for MI355X: brute-force incoherent de-dispersion (Magro et al. 2011).
+
+A thin ctypes binding over the C ABI in include/dedisp.h.  Every step of the
+computation runs in the HIP library; this module only marshals arguments.
+PyTorch supplies device memory (tensors) and streams.  If the library has
+not been built, every call raises `LibraryMissing`: there is no CPU fallback.
+
+    import torch, paper_1107_2516_amd as dd
+    plan = dd.Plan(nchans=1024, f_top=1510.0, df=296/1024, t_samp=64e-6, dms=dms)
+    out = plan.execute(x)        # x: [nchans, nsamp] float32/float16/uint8 on cuda
+"""
+import ctypes
+import os
+import re
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdedisp.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "dedisp.h")
+
+DD_OK = 0
+DD_ERR_INVALID_ARG = -1
+DD_ERR_DTYPE = -2
+DD_ERR_NSAMP = -3
+DD_ERR_OOM = -4
+DD_ERR_HIP = -5
+DD_ERR_AGAIN = -6
+DD_ERR_TOO_LARGE = -7
+DD_ERR_NOT_FOUND = -8
+DD_ERR_NOT_IMPLEMENTED = -9
+DD_ERR_STATE = -10
+
+DD_U8, DD_F16, DD_F32, DD_I32 = 1, 2, 3, 4
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class DedispError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+class TileConfig(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("dms_per_wave", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("tsamp_per_lane", ctypes.c_int32),
+                ("chans_per_stage", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_in", ctypes.c_void_p), ("nsamp", ctypes.c_int64),
+                ("in_stride", ctypes.c_int64), ("d_out", ctypes.c_void_p),
+                ("out_stride", ctypes.c_int64)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("in_t", ctypes.c_int), ("out_t", ctypes.c_int), ("max_inflight", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("nstreams", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("beam", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("seq", ctypes.c_int64), ("t_first", ctypes.c_int64), ("nout", ctypes.c_int64),
+                ("d_out", ctypes.c_void_p), ("out_stride", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+_SIGS = {
+    "dd_plan_create": [_I32, _D, _D, _D, _P, _I32, _PP],
+    "dd_plan_create_from_delays": [_I32, _I32, _P, _PP],
+    "dd_plan_info": [_P, _P, _P, _P],
+    "dd_delay_table": [_P, _P],
+    "dd_plan_destroy": [_P],
+    "dd_execute": [_P, _P, ctypes.c_int, _I64, _I64, _P, ctypes.c_int, _I64, _P],
+    "dd_batch_create": [_P, _I32, ctypes.c_int, ctypes.c_int, _PP],
+    "dd_batch_update": [_P, _P, _I32],
+    "dd_batch_launch": [_P, _P],
+    "dd_batch_destroy": [_P],
+    "dd_autotune": [_P, ctypes.c_int, _I64, _P, ctypes.POINTER(TileConfig), ctypes.POINTER(ctypes.c_float)],
+    "dd_tile_for": [_P, ctypes.c_int, _I64, ctypes.POINTER(TileConfig)],
+    "dd_serve_create": [ctypes.POINTER(ServeConfig), _P, ctypes.c_size_t, _PP],
+    "dd_serve_add_beam": [_P, _P, _I64, ctypes.POINTER(_I32)],
+    "dd_serve_submit": [_P, _I32, _P, _I64, _I64, ctypes.POINTER(ctypes.c_uint64)],
+    "dd_serve_poll": [_P, ctypes.POINTER(Result), _I32, ctypes.POINTER(_I32)],
+    "dd_serve_release": [_P, ctypes.c_uint64],
+    "dd_serve_drain": [_P],
+    "dd_serve_destroy": [_P],
+}
+
+
+def lib():
+    """The loaded libdedisp (raises LibraryMissing if it was never built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(
+                f"{LIB_PATH} is not built; run `python -m paper_1107_2516_amd.build` "
+                "(or __graft_entry__.build()). There is no CPU fallback.")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.dd_status_str.argtypes = [ctypes.c_int]
+        L.dd_status_str.restype = ctypes.c_char_p
+        L.dd_last_error.argtypes = []
+        L.dd_last_error.restype = ctypes.c_char_p
+        L.dd_version.argtypes = []
+        L.dd_version.restype = ctypes.c_char_p
+        _lib = L
+        return L
+
+
+def header_symbols():
+    """Every function the C header declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def status_str(status: int) -> str:
+    return lib().dd_status_str(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().dd_last_error().decode()
+
+
+def version() -> str:
+    return lib().dd_version().decode()
+
+
+def _check(status):
+    if status != DD_OK:
+        raise DedispError(status, last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(dtype) -> int:
+    torch = _torch()
+    m = {torch.float32: DD_F32, torch.float16: DD_F16, torch.uint8: DD_U8, torch.int32: DD_I32}
+    if dtype not in m:
+        raise DedispError(DD_ERR_DTYPE, f"unsupported dtype {dtype}")
+    return m[dtype]
+
+
+def out_dtype_for(in_dtype):
+    torch = _torch()
+    return torch.int32 if in_dtype == torch.uint8 else torch.float32
+
+
+def stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A de-dispersion plan: the FP64 delay table of section 3 ("Shifts")."""
+
+    def __init__(self, nchans=None, f_top=None, df=None, t_samp=None, dms=None, *, _handle=None):
+        L = lib()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            dms = np.ascontiguousarray(np.asarray(dms, dtype=np.float64).reshape(-1))
+            h = ctypes.c_void_p()
+            _check(L.dd_plan_create(int(nchans), float(f_top), float(df), float(t_samp),
+                                    dms.ctypes.data if dms.size else None, int(dms.size),
+                                    ctypes.byref(h)))
+            self._h = h
+        n, d, m = _I32(), _I32(), _I32()
+        _check(L.dd_plan_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(m)))
+        self.nchans, self.ndms, self.max_shift = n.value, d.value, m.value
+
+    @classmethod
+    def from_delays(cls, delays):
+        t = np.ascontiguousarray(np.asarray(delays), dtype=np.int32)
+        if t.ndim != 2:
+            raise DedispError(DD_ERR_INVALID_ARG, "delays must be [ndms, nchans]")
+        h = ctypes.c_void_p()
+        _check(lib().dd_plan_create_from_delays(int(t.shape[1]), int(t.shape[0]), t.ctypes.data,
+                                                ctypes.byref(h)))
+        return cls(_handle=h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def delay_table(self) -> np.ndarray:
+        out = np.empty((self.ndms, self.nchans), dtype=np.int32)
+        _check(lib().dd_delay_table(self._h, out.ctypes.data))
+        return out
+
+    def nout(self, nsamp: int) -> int:
+        return int(nsamp) - self.max_shift
+
+    def execute(self, inp, out=None, stream=None):
+        """De-disperse `inp` ([nchans, nsamp] on the GPU, rows may be padded)
+        into `out` ([ndms, >= nout]); allocates `out` if not given."""
+        torch = _torch()
+        if inp.dim() != 2 or inp.shape[0] != self.nchans:
+            raise DedispError(DD_ERR_INVALID_ARG, f"input must be [{self.nchans}, nsamp]")
+        if inp.stride(1) != 1:
+            raise DedispError(DD_ERR_INVALID_ARG, "time axis must be contiguous")
+        nsamp = inp.shape[1]
+        if out is None:
+            out = torch.empty((self.ndms, max(self.nout(nsamp), 0)), dtype=out_dtype_for(inp.dtype),
+                              device=inp.device)
+        if out.dim() != 2 or out.stride(1) != 1 or out.shape[0] != self.ndms:
+            raise DedispError(DD_ERR_INVALID_ARG, f"output must be [{self.ndms}, nout] row-major")
+        if not inp.is_cuda or not out.is_cuda:
+            raise DedispError(DD_ERR_INVALID_ARG, "tensors must be on the GPU")
+        _check(lib().dd_execute(self._h, inp.data_ptr(), dtype_code(inp.dtype), nsamp,
+                                inp.stride(0), out.data_ptr(), dtype_code(out.dtype),
+                                out.stride(0), stream_handle(stream)))
+        return out
+
+    def tile_for(self, in_dtype, nsamp):
+        cfg = TileConfig()
+        _check(lib().dd_tile_for(self._h, dtype_code(in_dtype), int(nsamp), ctypes.byref(cfg)))
+        return cfg.as_dict()
+
+    def autotune(self, in_dtype, nsamp, stream=None):
+        cfg = TileConfig()
+        ms = ctypes.c_float()
+        _check(lib().dd_autotune(self._h, dtype_code(in_dtype), int(nsamp), stream_handle(stream),
+                                 ctypes.byref(cfg), ctypes.byref(ms)))
+        return cfg.as_dict(), ms.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,132 @@
+// C ABI of libdedisp: argument checking and dispatch.  Every entry point
+// catches C++ exceptions and reports them as a dd_status.
+#include <cstring>
+#include <new>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+dd_status set_error(dd_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+dd_status hip_error(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return DD_ERR_HIP;
+}
+
+}  // namespace dd
+
+#define DD_GUARD_BEGIN try {
+#define DD_GUARD_END                                                   \
+  }                                                                    \
+  catch (const std::bad_alloc&) {                                      \
+    return dd::set_error(DD_ERR_OOM, "host allocation failed");        \
+  }                                                                    \
+  catch (const std::exception& ex) {                                   \
+    return dd::set_error(DD_ERR_INVALID_ARG, ex.what());               \
+  }                                                                    \
+  catch (...) {                                                        \
+    return dd::set_error(DD_ERR_INVALID_ARG, "unknown C++ exception"); \
+  }
+
+extern "C" {
+
+dd_status dd_plan_create(int32_t nchans, double f_top_mhz, double df_mhz, double t_samp_s,
+                         const double* dm_list, int32_t ndms, dd_plan** out) {
+  DD_GUARD_BEGIN
+  return dd::plan_from_law(nchans, f_top_mhz, df_mhz, t_samp_s, dm_list, ndms, out);
+  DD_GUARD_END
+}
+
+dd_status dd_plan_create_from_delays(int32_t nchans, int32_t ndms, const int32_t* delays,
+                                     dd_plan** out) {
+  DD_GUARD_BEGIN
+  return dd::plan_from_table(nchans, ndms, delays, out);
+  DD_GUARD_END
+}
+
+dd_status dd_plan_info(const dd_plan* plan, int32_t* nchans, int32_t* ndms, int32_t* max_shift) {
+  if (!plan) return dd::set_error(DD_ERR_INVALID_ARG, "plan is NULL");
+  if (nchans) *nchans = plan->nchans;
+  if (ndms) *ndms = plan->ndms;
+  if (max_shift) *max_shift = plan->max_shift;
+  return DD_OK;
+}
+
+dd_status dd_delay_table(const dd_plan* plan, int32_t* host_out) {
+  if (!plan || !host_out) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  std::memcpy(host_out, plan->delays.data(), plan->delays.size() * sizeof(int32_t));
+  return DD_OK;
+}
+
+dd_status dd_plan_destroy(dd_plan* plan) {
+  DD_GUARD_BEGIN
+  delete plan;
+  return DD_OK;
+  DD_GUARD_END
+}
+
+dd_status dd_execute(const dd_plan* cplan, const void* d_in, dd_dtype in_t, int64_t nsamp,
+                     int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
+                     void* stream) {
+  DD_GUARD_BEGIN
+  if (!cplan || !d_in || !d_out) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  if (!dd::dtype_pair_ok(in_t, out_t))
+    return dd::set_error(DD_ERR_DTYPE, "supported pairs: f32->f32, f16->f32, u8->i32");
+  dd_plan* plan = const_cast<dd_plan*>(cplan);  // only its lazily built device cache changes
+  if (nsamp <= plan->max_shift)
+    return dd::set_error(DD_ERR_NSAMP, "nsamp must exceed the plan's max_shift");
+  const int64_t nout = nsamp - plan->max_shift;
+  if (in_stride < nsamp || out_stride < nout)
+    return dd::set_error(DD_ERR_INVALID_ARG, "stride smaller than the row length");
+  dd::TileShape s = dd::shape_for(plan, in_t, nsamp);
+  const dd::TileTables* tt = nullptr;
+  dd_status st = dd::plan_tiles(plan, s.dms_per_tile(), &tt);
+  if (st != DD_OK) return st;
+  dd::ExecArgs a{d_in, nsamp, in_stride, d_out, out_stride, nout, plan->nchans};
+  return dd::launch_dedisperse(s, *tt, in_t, a, static_cast<hipStream_t>(stream));
+  DD_GUARD_END
+}
+
+dd_status dd_tile_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, dd_tile_config* cfg) {
+  if (!plan || !cfg) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  dd::TileShape s = dd::shape_for(plan, in_t, nsamp);
+  cfg->variant = s.variant;
+  cfg->dms_per_wave = s.dms_per_wave;
+  cfg->waves = s.waves;
+  cfg->tsamp_per_lane = s.tsamp_per_lane;
+  cfg->chans_per_stage = s.chans_per_stage;
+  return DD_OK;
+}
+
+const char* dd_status_str(dd_status s) {
+  switch (s) {
+    case DD_OK: return "DD_OK";
+    case DD_ERR_INVALID_ARG: return "DD_ERR_INVALID_ARG";
+    case DD_ERR_DTYPE: return "DD_ERR_DTYPE";
+    case DD_ERR_NSAMP: return "DD_ERR_NSAMP";
+    case DD_ERR_OOM: return "DD_ERR_OOM";
+    case DD_ERR_HIP: return "DD_ERR_HIP";
+    case DD_ERR_AGAIN: return "DD_ERR_AGAIN";
+    case DD_ERR_TOO_LARGE: return "DD_ERR_TOO_LARGE";
+    case DD_ERR_NOT_FOUND: return "DD_ERR_NOT_FOUND";
+    case DD_ERR_NOT_IMPLEMENTED: return "DD_ERR_NOT_IMPLEMENTED";
+    case DD_ERR_STATE: return "DD_ERR_STATE";
+  }
+  return "DD_ERR_UNKNOWN";
+}
+
+const char* dd_last_error(void) { return dd::last_error_cstr(); }
+
+const char* dd_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal declarations shared by the libdedisp sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dedisp.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------- errors
+dd_status set_error(dd_status s, const std::string& msg);
+dd_status hip_error(hipError_t e, const char* what);
+const char* last_error_cstr();
+#define DD_HIP(call)                                    \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return dd::hip_error(e_, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------- tiling
+// A tile shape: a workgroup of `waves` wavefronts covers waves*dms_per_wave
+// DM trials (a "DM tile") and 64*tsamp_per_lane output samples (a "time
+// tile"); `chans_per_stage` channels are staged in LDS per step.
+struct TileShape {
+  int variant = 0;
+  int dms_per_wave = 8;
+  int waves = 4;
+  int tsamp_per_lane = 8;
+  int chans_per_stage = 8;
+  int dms_per_tile() const { return waves * dms_per_wave; }
+  int tsamp_per_tile() const { return 64 * tsamp_per_lane; }
+  bool operator<(const TileShape& o) const {
+    return std::tie(variant, dms_per_wave, waves, tsamp_per_lane, chans_per_stage) <
+           std::tie(o.variant, o.dms_per_wave, o.waves, o.tsamp_per_lane, o.chans_per_stage);
+  }
+};
+
+// Device tables of one plan for one DM-tile height on one device.
+//   base[tile*nchans + c]       smallest delay of channel c within the tile
+//   rel[(tile*nchans + c)*TD+j] delay of the tile's j-th DM minus base
+//   rows[tile*TD + j]           caller's row index of that DM (-1 = padding)
+// DMs are grouped into tiles after sorting by their delay at the lowest
+// channel, so each tile holds DMs with similar shifts whatever the caller's
+// DM order.
+struct TileTables {
+  int td = 0;
+  int ntiles = 0;
+  int span_max = 0;  // largest rel entry over all tiles and channels
+  std::vector<int> span_tile;  // per tile, largest rel entry over channels
+  int32_t* d_base = nullptr;
+  int32_t* d_rel = nullptr;
+  int32_t* d_rows = nullptr;
+};
+
+struct DeviceTables {
+  std::map<int, TileTables> by_td;
+};
+
+}  // namespace dd
+
+struct dd_plan {
+  int32_t nchans = 0;
+  int32_t ndms = 0;
+  int32_t max_shift = 0;
+  std::vector<int32_t> delays;  // host table [ndms][nchans]
+  std::vector<int32_t> order;   // DM indices sorted by delay at the last channel
+  std::mutex mu;
+  std::map<int, dd::DeviceTables> dev;  // keyed by HIP device ordinal
+  ~dd_plan();
+};
+
+namespace dd {
+
+// Host-side plan construction (dd_plan.cpp).
+dd_status plan_from_law(int32_t nchans, double f_top, double df, double t_samp, const double* dms,
+                        int32_t ndms, dd_plan** out);
+dd_status plan_from_table(int32_t nchans, int32_t ndms, const int32_t* delays, dd_plan** out);
+
+// Uploads (once per device) and returns the tile tables for height td.
+dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out);
+
+// Kernel launchers (dd_kernels.hip).
+struct ExecArgs {
+  const void* in;
+  int64_t nsamp, in_stride;
+  void* out;
+  int64_t out_stride, nout;
+  int32_t nchans;
+};
+bool dtype_pair_ok(dd_dtype in_t, dd_dtype out_t);
+size_t dtype_size(dd_dtype t);
+TileShape default_shape(dd_dtype in_t, const dd_plan* plan);
+dd_status launch_dedisperse(const TileShape& shape, const TileTables& tt, dd_dtype in_t,
+                            const ExecArgs& a, hipStream_t stream);
+
+// Tile-shape selection (dd_tune.cpp).
+TileShape shape_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp);
+
+}  // namespace dd

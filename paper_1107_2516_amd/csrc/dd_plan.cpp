@@ -1,0 +1,174 @@
+// Plans: the host FP64 delay table of section 3 ("Shifts") and the per-device
+// tile tables the kernels read.
+//
+// This file is compiled with -ffp-contract=off so that every FP64 product,
+// quotient and difference below is rounded on its own, in the order written.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+namespace {
+
+constexpr double kDispersionSeconds = 4150.0;  // 4.15e6 ms (section 1), in s MHz^2 / (pc cm^-3)
+
+// Shift in samples of channel frequency f_c relative to f_top for one DM:
+// t_chan = 4150 (f_c^-2 - f_top^-2) seconds per unit DM (section 3 "Shifts",
+// first equation), then t_DM = t_chan * DM / t_samp (second equation),
+// rounded to the nearest sample with ties away from zero.
+int64_t shift_samples(double f_c, double f_top, double dm, double t_samp) {
+  const double t_chan = kDispersionSeconds * (1.0 / (f_c * f_c) - 1.0 / (f_top * f_top));
+  return std::llround(t_chan * dm / t_samp);
+}
+
+dd_status finish_plan(dd_plan* p, dd_plan** out) {
+  int64_t mx = 0;
+  for (int32_t v : p->delays) mx = std::max<int64_t>(mx, v);
+  p->max_shift = static_cast<int32_t>(mx);
+  // Tile order: DMs sorted by their delay at the lowest channel (stable, so
+  // equal rows keep the caller's order).  For an increasing DM list this is
+  // the identity.
+  p->order.resize(p->ndms);
+  std::iota(p->order.begin(), p->order.end(), 0);
+  const int32_t last = p->nchans - 1;
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int32_t a, int32_t b) {
+    return p->delays[(size_t)a * p->nchans + last] < p->delays[(size_t)b * p->nchans + last];
+  });
+  *out = p;
+  return DD_OK;
+}
+
+}  // namespace
+
+dd_status plan_from_law(int32_t nchans, double f_top, double df, double t_samp, const double* dms,
+                        int32_t ndms, dd_plan** out) {
+  if (!out) return set_error(DD_ERR_INVALID_ARG, "out is NULL");
+  if (nchans < 1 || nchans > (1 << 23)) return set_error(DD_ERR_INVALID_ARG, "nchans out of range");
+  if (ndms < 1 || !dms) return set_error(DD_ERR_INVALID_ARG, "need at least one DM");
+  if (!std::isfinite(f_top) || !std::isfinite(df) || !std::isfinite(t_samp) || !(df > 0.0) ||
+      !(t_samp > 0.0))
+    return set_error(DD_ERR_INVALID_ARG, "f_top, df and t_samp must be finite, df and t_samp > 0");
+  const double f_low = f_top - static_cast<double>(nchans - 1) * df;
+  if (!(f_low > 0.0)) return set_error(DD_ERR_INVALID_ARG, "lowest channel frequency must be > 0");
+  for (int32_t d = 0; d < ndms; d++)
+    if (!std::isfinite(dms[d]) || dms[d] < 0.0)
+      return set_error(DD_ERR_INVALID_ARG, "every DM must be finite and >= 0");
+
+  std::unique_ptr<dd_plan> p(new (std::nothrow) dd_plan());
+  if (!p) return set_error(DD_ERR_OOM, "plan allocation");
+  p->nchans = nchans;
+  p->ndms = ndms;
+  try {
+    p->delays.resize(static_cast<size_t>(nchans) * ndms);
+  } catch (...) {
+    return set_error(DD_ERR_OOM, "delay table allocation");
+  }
+  for (int32_t c = 0; c < nchans; c++) {
+    const double f_c = f_top - static_cast<double>(c) * df;
+    for (int32_t d = 0; d < ndms; d++) {
+      const int64_t s = shift_samples(f_c, f_top, dms[d], t_samp);
+      if (s < 0 || s > INT32_MAX / 2)
+        return set_error(DD_ERR_INVALID_ARG, "delay does not fit the int32 table");
+      p->delays[static_cast<size_t>(d) * nchans + c] = static_cast<int32_t>(s);
+    }
+  }
+  return finish_plan(p.release(), out);
+}
+
+dd_status plan_from_table(int32_t nchans, int32_t ndms, const int32_t* delays, dd_plan** out) {
+  if (!out || !delays) return set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  if (nchans < 1 || nchans > (1 << 23) || ndms < 1)
+    return set_error(DD_ERR_INVALID_ARG, "sizes out of range");
+  const size_t n = static_cast<size_t>(nchans) * ndms;
+  for (size_t i = 0; i < n; i++)
+    if (delays[i] < 0 || delays[i] > INT32_MAX / 2)
+      return set_error(DD_ERR_INVALID_ARG, "delays must be in [0, 2^30)");
+  std::unique_ptr<dd_plan> p(new (std::nothrow) dd_plan());
+  if (!p) return set_error(DD_ERR_OOM, "plan allocation");
+  p->nchans = nchans;
+  p->ndms = ndms;
+  try {
+    p->delays.assign(delays, delays + n);
+  } catch (...) {
+    return set_error(DD_ERR_OOM, "delay table allocation");
+  }
+  return finish_plan(p.release(), out);
+}
+
+dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out) {
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceTables& dt = plan->dev[dev];
+  auto it = dt.by_td.find(td);
+  if (it != dt.by_td.end()) {
+    *out = &it->second;
+    return DD_OK;
+  }
+  const int nch = plan->nchans;
+  const int ntiles = (plan->ndms + td - 1) / td;
+  std::vector<int32_t> base(static_cast<size_t>(ntiles) * nch);
+  std::vector<int32_t> rel(static_cast<size_t>(ntiles) * nch * td);
+  std::vector<int32_t> rows(static_cast<size_t>(ntiles) * td, -1);
+  TileTables tt;
+  tt.td = td;
+  tt.ntiles = ntiles;
+  tt.span_tile.assign(ntiles, 0);
+  for (int tile = 0; tile < ntiles; tile++) {
+    const int first = tile * td;
+    const int count = std::min(td, plan->ndms - first);
+    for (int j = 0; j < td; j++)
+      rows[static_cast<size_t>(tile) * td + j] = j < count ? plan->order[first + j] : -1;
+    for (int c = 0; c < nch; c++) {
+      int32_t lo = INT32_MAX;
+      for (int j = 0; j < count; j++)
+        lo = std::min(lo, plan->delays[static_cast<size_t>(plan->order[first + j]) * nch + c]);
+      base[static_cast<size_t>(tile) * nch + c] = lo;
+      for (int j = 0; j < td; j++) {
+        // padding DMs repeat the tile's first DM; their sums are not stored
+        const int src = plan->order[first + (j < count ? j : 0)];
+        const int32_t r = plan->delays[static_cast<size_t>(src) * nch + c] - lo;
+        rel[(static_cast<size_t>(tile) * nch + c) * td + j] = r;
+        tt.span_tile[tile] = std::max(tt.span_tile[tile], static_cast<int>(r));
+      }
+    }
+    tt.span_max = std::max(tt.span_max, tt.span_tile[tile]);
+  }
+  hipError_t e = hipMalloc(&tt.d_base, base.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&tt.d_rel, rel.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&tt.d_rows, rows.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(tt.d_base, base.data(), base.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(tt.d_rel, rel.data(), rel.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(tt.d_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(tt.d_base);
+    (void)hipFree(tt.d_rel);
+    (void)hipFree(tt.d_rows);
+    return hip_error(e, "uploading tile tables");
+  }
+  auto res = dt.by_td.emplace(td, std::move(tt));
+  *out = &res.first->second;
+  return DD_OK;
+}
+
+}  // namespace dd
+
+dd_plan::~dd_plan() {
+  for (auto& kv : dev) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(kv.first);
+    for (auto& t : kv.second.by_td) {
+      (void)hipFree(t.second.d_base);
+      (void)hipFree(t.second.d_rel);
+      (void)hipFree(t.second.d_rows);
+    }
+    (void)hipSetDevice(cur);
+  }
+}

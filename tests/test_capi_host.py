@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, builds delay tables that equal the
+oracle's bit for bit, and reports argument errors with status codes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1107_2516_amd as dd
+import synth
+
+
+def test_library_exports_every_header_symbol():
+    L = dd.lib()
+    syms = dd.header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+    assert dd.version().count(".") == 2
+
+
+def _configs():
+    out = [("tiny", synth.tiny().band, synth.tiny().dms),
+           ("scale", synth.scale().band, synth.scale().dms),
+           ("serve", synth.serve_band(), synth.dm_grid(4096, 0.125)),
+           ("paper_table2", synth.paper_table2().band, synth.paper_table2().dms)]
+    for b in synth.batch_beams()[:4]:
+        out.append((f"batch{b['band'].nchans}_{b['ndms']}", b["band"], synth.dm_grid(b["ndms"], b["step"])))
+    return out
+
+
+@pytest.mark.parametrize("name,band,dms", _configs(), ids=[c[0] for c in _configs()])
+def test_delay_table_matches_oracle(name, band, dms):
+    p = dd.Plan(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    ref = oracle.delay_table(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    t = p.delay_table()
+    assert t.shape == ref.shape
+    assert np.array_equal(t.astype(np.int64), ref)
+    assert p.max_shift == oracle.max_shift(ref)
+    assert p.nchans == band.nchans and p.ndms == len(dms)
+
+
+def test_unsorted_and_duplicate_dms():
+    b = synth.tiny().band
+    dms = np.array([7.0, 0.0, 12.5, 7.0, 3.25, 0.1])
+    p = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, dms)
+    ref = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, dms)
+    assert np.array_equal(p.delay_table(), ref)
+
+
+def test_from_delays_roundtrip():
+    g = np.random.default_rng(0)
+    t = g.integers(0, 1000, (37, 11)).astype(np.int32)
+    p = dd.Plan.from_delays(t)
+    assert np.array_equal(p.delay_table(), t)
+    assert p.max_shift == t.max() and p.ndms == 37 and p.nchans == 11
+
+
+@pytest.mark.parametrize("args", [
+    (0, 432.0, 0.5, 64e-6, [1.0]),
+    (64, 432.0, 0.0, 64e-6, [1.0]),
+    (64, 432.0, -0.5, 64e-6, [1.0]),
+    (64, 432.0, 0.5, 0.0, [1.0]),
+    (64, 432.0, 0.5, -1e-6, [1.0]),
+    (1000, 432.0, 0.5, 64e-6, [1.0]),
+    (64, 432.0, 0.5, 64e-6, [-1.0]),
+    (64, 432.0, 0.5, 64e-6, [float("nan")]),
+    (64, float("inf"), 0.5, 64e-6, [1.0]),
+    (64, 432.0, 0.5, 64e-6, []),
+])
+def test_plan_argument_errors(args):
+    with pytest.raises(dd.DedispError) as ei:
+        dd.Plan(*args)
+    assert ei.value.status == dd.DD_ERR_INVALID_ARG
+
+
+def test_from_delays_rejects_negative():
+    with pytest.raises(dd.DedispError) as ei:
+        dd.Plan.from_delays(np.array([[0, -3]], dtype=np.int32))
+    assert ei.value.status == dd.DD_ERR_INVALID_ARG
+
+
+def test_null_arguments_and_status_strings():
+    L = dd.lib()
+    assert L.dd_plan_info(None, None, None, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_delay_table(None, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_execute(None, None, dd.DD_F32, 10, 10, None, dd.DD_F32, 10, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_plan_destroy(None) == dd.DD_OK
+    for code in range(-10, 1):
+        assert dd.status_str(code).startswith("DD_")
+    out = ctypes.c_void_p()
+    assert L.dd_plan_create(4, 100.0, 1.0, 1e-3, None, 1, ctypes.byref(out)) == dd.DD_ERR_INVALID_ARG
+    assert "DM" in dd.last_error()
+
+
+def test_execute_argument_errors_before_any_gpu_work():
+    """Type-pair and nsamp checks happen before the library touches the GPU."""
+    L = dd.lib()
+    b = synth.tiny().band
+    p = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, [0.0, 5.0])
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the call fails first
+    assert L.dd_execute(p.handle, fake, dd.DD_F32, 100000, 100000, fake, dd.DD_I32, 100000, None) == dd.DD_ERR_DTYPE
+    assert L.dd_execute(p.handle, fake, dd.DD_U8, 100000, 100000, fake, dd.DD_F32, 100000, None) == dd.DD_ERR_DTYPE
+    assert L.dd_execute(p.handle, fake, dd.DD_F32, p.max_shift, p.max_shift, fake, dd.DD_F32, 1, None) == dd.DD_ERR_NSAMP
+    assert L.dd_execute(p.handle, fake, dd.DD_F32, 1000, 999, fake, dd.DD_F32, 1000, None) == dd.DD_ERR_INVALID_ARG

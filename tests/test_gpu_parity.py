@@ -1,0 +1,171 @@
+"""GPU parity: the HIP kernels through the C ABI against the CPU oracle.
+
+Bars: 8-bit inputs and integer-valued float inputs bit-exact; FP32 and FP16
+inputs within scaled error 1e-5 of the FP64 oracle (helpers.FP_TOL).
+Shapes span several DM tiles, several time tiles and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1107_2516_amd as dd
+import synth
+from helpers import FP_TOL, make_input, rand_table, scaled_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _run(plan, x, out=None):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    o = plan.execute(xt, out=out)
+    torch.cuda.synchronize()
+    return o.cpu().numpy()
+
+
+def _check(plan, x, tab, dtype):
+    y = _run(plan, x)
+    if dtype == "u8":
+        ref = oracle.dedisperse(x, tab)
+        assert y.dtype == np.int32
+        assert np.array_equal(y.astype(np.int64), ref)
+    else:
+        e, _ = scaled_error(y, x, tab)
+        assert e <= FP_TOL, e
+
+
+def test_tiny_workload_matches_oracle_and_finds_pulse():
+    w = synth.tiny()
+    b = w.band
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
+    tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
+    x = synth.noise(b.nchans, w.nsamp, w.seed)
+    e = w.extra
+    synth.add_boxcar(x, tab[50], e["pulse_t0"], e["pulse_width"], e["pulse_amp"])
+    y = _run(plan, x)
+    assert y.shape == (128, w.nsamp - 721)
+    err, _ = scaled_error(y, x, tab)
+    assert err <= FP_TOL, err
+    s = oracle.snr(y, width=e["pulse_width"])
+    d, t = np.unravel_index(np.argmax(s), s.shape)
+    assert d == 50 and abs(t - e["pulse_t0"]) <= 1
+
+
+SHAPES = [
+    # nchans, ndms, nsamp, max delay: ragged against every tile dimension
+    (1, 1, 10, 0),
+    (5, 33, 600, 50),
+    (37, 45, 3000, 200),
+    (130, 70, 1500, 300),
+    (64, 128, 8192, 721),
+    (9, 200, 1100, 1000),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "u8"])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}x{s[2]}" for s in SHAPES])
+def test_random_tables(dtype, shape):
+    nchans, ndms, nsamp, maxd = shape
+    g = np.random.default_rng(["f32", "f16", "u8"].index(dtype) * 1000 + sum(shape))
+    tab = rand_table(g, ndms, nchans, maxd)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, dtype, nchans, nsamp)
+    _check(plan, x, tab, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_integer_valued_floats_are_exact(dtype):
+    g = np.random.default_rng(11)
+    tab = rand_table(g, 40, 100, 300)
+    xi = g.integers(-100, 100, (100, 2000))
+    x = xi.astype(np.float32 if dtype == "f32" else np.float16)
+    y = _run(dd.Plan.from_delays(tab), x)
+    assert np.array_equal(y.astype(np.float64), oracle.dedisperse(x, tab))
+
+
+def test_dm_zero_is_channel_sum_and_constant_input():
+    b = synth.tiny().band
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, [0.0, 0.0, 3.0])
+    g = np.random.default_rng(3)
+    x = g.integers(0, 256, (b.nchans, 5000)).astype(np.uint8)
+    y = _run(plan, x)
+    assert np.array_equal(y[0], x.astype(np.int64).sum(0)[: y.shape[1]])
+    assert np.array_equal(y[1], y[0])
+    c = np.full((b.nchans, 5000), 0.75, dtype=np.float32)
+    yc = _run(plan, c)
+    assert (yc == 0.75 * b.nchans).all()
+
+
+def test_unit_impulse_lands_at_every_shift():
+    g = np.random.default_rng(4)
+    nchans, ndms, nsamp = 21, 70, 700
+    tab = rand_table(g, ndms, nchans, 150)
+    plan = dd.Plan.from_delays(tab)
+    nout = nsamp - tab.max()
+    for c0 in range(nchans):
+        x = np.zeros((nchans, nsamp), dtype=np.uint8)
+        x[c0, 400] = 1
+        y = _run(plan, x)
+        for d in range(ndms):
+            t = 400 - tab[d, c0]
+            exp = np.zeros(nout, dtype=np.int64)
+            if 0 <= t < nout:
+                exp[t] = 1
+            assert np.array_equal(y[d], exp), (c0, d)
+
+
+def test_unsorted_duplicate_dms():
+    b = synth.tiny().band
+    dms = np.array([12.7, 0.0, 5.0, 12.7, 0.3, 9.9, 5.0] * 7)
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, dms)
+    tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, dms)
+    x = make_input(np.random.default_rng(5), "u8", b.nchans, 3000)
+    _check(plan, x, tab, "u8")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+def test_padded_strides_and_tail_untouched(dtype):
+    g = np.random.default_rng(6)
+    nchans, ndms, nsamp = 33, 50, 1800
+    tab = rand_table(g, ndms, nchans, 260)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, dtype, nchans, nsamp)
+    big = np.zeros((nchans, nsamp + 77), dtype=x.dtype)
+    big[:, :nsamp] = x
+    xt = torch.from_numpy(big).cuda()[:, :nsamp]
+    nout = plan.nout(nsamp)
+    odt = torch.int32 if dtype == "u8" else torch.float32
+    sentinel = -12345
+    ob = torch.full((ndms, nout + 50), sentinel, dtype=odt, device="cuda")
+    plan.execute(xt, out=ob[:, :nout])
+    torch.cuda.synchronize()
+    y = ob.cpu().numpy()
+    assert (y[:, nout:] == sentinel).all()
+    if dtype == "u8":
+        assert np.array_equal(y[:, :nout].astype(np.int64), oracle.dedisperse(x, tab))
+    else:
+        e, _ = scaled_error(y[:, :nout], x, tab)
+        assert e <= FP_TOL
+
+
+def test_single_output_sample():
+    g = np.random.default_rng(7)
+    tab = rand_table(g, 17, 29, 400)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, "u8", 29, int(tab.max()) + 1)
+    y = _run(plan, x)
+    assert y.shape == (17, 1)
+    assert np.array_equal(y.astype(np.int64), oracle.dedisperse(x, tab))
+
+
+def test_errors_from_execute():
+    b = synth.tiny().band
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, [0.0, 12.7])
+    x = torch.zeros((b.nchans, plan.max_shift), dtype=torch.float32, device="cuda")
+    with pytest.raises(dd.DedispError) as ei:
+        plan.execute(x, out=torch.zeros((2, 1), device="cuda"))
+    assert ei.value.status == dd.DD_ERR_NSAMP
+    x = torch.zeros((b.nchans, 2000), dtype=torch.float32, device="cuda")
+    with pytest.raises(dd.DedispError) as ei:
+        plan.execute(x, out=torch.zeros((2, 2000), dtype=torch.int32, device="cuda"))
+    assert ei.value.status == dd.DD_ERR_DTYPE
