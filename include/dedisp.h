@@ -170,6 +170,17 @@ typedef struct dd_tile_config {
 dd_status dd_autotune(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, void* stream,
                       dd_tile_config* best, float* best_ms);
 
+/*
+ * dd_execute with an explicit tile shape (from dd_tile_for or dd_autotune, or
+ * chosen by the caller).  DD_ERR_NOT_IMPLEMENTED if no kernel exists for the
+ * shape and type pair; DD_ERR_TOO_LARGE if the plan's shift spread inside one
+ * DM tile does not fit the shape's LDS staging.  Results equal dd_execute's
+ * (bit-exact for 8-bit input, within the FP32 tolerance otherwise).
+ */
+dd_status dd_execute_tiled(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
+                           int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
+                           const dd_tile_config* cfg, void* stream);
+
 /* The tile shape dd_execute would use now for (plan, in_t, nsamp). */
 dd_status dd_tile_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, dd_tile_config* cfg);
 

@@ -92,6 +92,8 @@ _SIGS = {
     "dd_batch_update": [_P, _P, _I32],
     "dd_batch_launch": [_P, _P],
     "dd_batch_destroy": [_P],
+    "dd_execute_tiled": [_P, _P, ctypes.c_int, _I64, _I64, _P, ctypes.c_int, _I64,
+                         ctypes.POINTER(TileConfig), _P],
     "dd_autotune": [_P, ctypes.c_int, _I64, _P, ctypes.POINTER(TileConfig), ctypes.POINTER(ctypes.c_float)],
     "dd_tile_for": [_P, ctypes.c_int, _I64, ctypes.POINTER(TileConfig)],
     "dd_serve_create": [ctypes.POINTER(ServeConfig), _P, ctypes.c_size_t, _PP],
@@ -236,6 +238,19 @@ class Plan:
         _check(lib().dd_execute(self._h, inp.data_ptr(), dtype_code(inp.dtype), nsamp,
                                 inp.stride(0), out.data_ptr(), dtype_code(out.dtype),
                                 out.stride(0), stream_handle(stream)))
+        return out
+
+    def execute_tiled(self, inp, tile, out=None, stream=None):
+        """execute() with an explicit tile shape (a dict of TileConfig fields)."""
+        torch = _torch()
+        nsamp = inp.shape[1]
+        if out is None:
+            out = torch.empty((self.ndms, max(self.nout(nsamp), 0)), dtype=out_dtype_for(inp.dtype),
+                              device=inp.device)
+        cfg = TileConfig(**tile)
+        _check(lib().dd_execute_tiled(self._h, inp.data_ptr(), dtype_code(inp.dtype), nsamp,
+                                      inp.stride(0), out.data_ptr(), dtype_code(out.dtype),
+                                      out.stride(0), ctypes.byref(cfg), stream_handle(stream)))
         return out
 
     def tile_for(self, in_dtype, nsamp):

@@ -75,10 +75,13 @@ dd_status dd_plan_destroy(dd_plan* plan) {
   DD_GUARD_END
 }
 
-dd_status dd_execute(const dd_plan* cplan, const void* d_in, dd_dtype in_t, int64_t nsamp,
-                     int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
-                     void* stream) {
-  DD_GUARD_BEGIN
+}  // extern "C"
+
+namespace {
+
+dd_status execute_common(const dd_plan* cplan, const void* d_in, dd_dtype in_t, int64_t nsamp,
+                         int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
+                         const dd::TileShape* forced, void* stream) {
   if (!cplan || !d_in || !d_out) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
   if (!dd::dtype_pair_ok(in_t, out_t))
     return dd::set_error(DD_ERR_DTYPE, "supported pairs: f32->f32, f16->f32, u8->i32");
@@ -88,12 +91,49 @@ dd_status dd_execute(const dd_plan* cplan, const void* d_in, dd_dtype in_t, int6
   const int64_t nout = nsamp - plan->max_shift;
   if (in_stride < nsamp || out_stride < nout)
     return dd::set_error(DD_ERR_INVALID_ARG, "stride smaller than the row length");
-  dd::TileShape s = dd::shape_for(plan, in_t, nsamp);
+  dd::TileShape s = forced ? *forced : dd::shape_for(plan, in_t, nsamp);
+  if (s.dms_per_wave < 1 || s.waves < 1 || s.tsamp_per_lane < 1 || s.chans_per_stage < 1)
+    return dd::set_error(DD_ERR_INVALID_ARG, "tile shape fields must be >= 1");
+  dd::ExecArgs a{d_in, nsamp, in_stride, d_out, out_stride, nout, plan->nchans};
   const dd::TileTables* tt = nullptr;
   dd_status st = dd::plan_tiles(plan, s.dms_per_tile(), &tt);
   if (st != DD_OK) return st;
-  dd::ExecArgs a{d_in, nsamp, in_stride, d_out, out_stride, nout, plan->nchans};
-  return dd::launch_dedisperse(s, *tt, in_t, a, static_cast<hipStream_t>(stream));
+  st = dd::launch_dedisperse(s, *tt, in_t, a, static_cast<hipStream_t>(stream));
+  if (st == DD_ERR_TOO_LARGE && !forced && s.variant != 0) {
+    // the shift spread of this plan does not fit the fast variant's staging
+    s = dd::default_shape(in_t, plan);
+    st = dd::plan_tiles(plan, s.dms_per_tile(), &tt);
+    if (st != DD_OK) return st;
+    st = dd::launch_dedisperse(s, *tt, in_t, a, static_cast<hipStream_t>(stream));
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_execute(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
+                     int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
+                     void* stream) {
+  DD_GUARD_BEGIN
+  return execute_common(plan, d_in, in_t, nsamp, in_stride, d_out, out_t, out_stride, nullptr,
+                        stream);
+  DD_GUARD_END
+}
+
+dd_status dd_execute_tiled(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
+                           int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
+                           const dd_tile_config* cfg, void* stream) {
+  DD_GUARD_BEGIN
+  if (!cfg) return dd::set_error(DD_ERR_INVALID_ARG, "cfg is NULL");
+  dd::TileShape s;
+  s.variant = cfg->variant;
+  s.dms_per_wave = cfg->dms_per_wave;
+  s.waves = cfg->waves;
+  s.tsamp_per_lane = cfg->tsamp_per_lane;
+  s.chans_per_stage = cfg->chans_per_stage;
+  return execute_common(plan, d_in, in_t, nsamp, in_stride, d_out, out_t, out_stride, &s, stream);
   DD_GUARD_END
 }
 

@@ -26,6 +26,8 @@
 namespace dd {
 namespace {
 
+#include "dd_window_asm.inc"
+
 template <typename T>
 struct Acc;
 template <>
@@ -118,6 +120,100 @@ __global__ __launch_bounds__(256) void k_dedisp_lds(KParams p) {
   }
 }
 
+
+// Register-window variant for FP32 input.  Same tiling as k_dedisp_lds, but
+// lane l owns K *consecutive* samples t0 + l*K + k, so the samples a lane
+// needs for all DMs of its wavefront at one channel are a few overlapping
+// K-long runs of the staged window.  STEP (generated inline assembly,
+// dd_window_asm.inc) loads a register window once and serves every DM whose
+// run fits in it through VGPR-relative addressing.  K is 4 mod 8 so the
+// 16-byte window reads of 64 lanes (stride 4K bytes) hit distinct LDS banks.
+//
+// Staging is asynchronous and double-buffered: the channels of stage s+1 are
+// copied global -> LDS by buffer loads that write LDS directly (no VGPRs),
+// issued before stage s is computed.  The buffer descriptor of each channel
+// row bounds reads at nsamp samples, so samples past the end read as zero
+// (they only feed outputs t >= nout, which are not stored).
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int DW, int K, int WMAX, int OCC, void (*STEP)(float*, const int*, unsigned)>
+__global__ __launch_bounds__(256, OCC) void k_dedisp_win_f32(KParams p,
+                                                           const int32_t* __restrict__ rel,
+                                                           const int32_t* __restrict__ base) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* lds = reinterpret_cast<float*>(smem);
+  constexpr int TD = 4 * DW, TT = 64 * K;
+  const int b = blockIdx.x;
+  const int w = (b & 7) * p.per_xcd + (b >> 3);
+  if (w >= p.nblocks) return;
+  const int dtile = w % p.n_dtiles;
+  const int ttile = w / p.n_dtiles;
+  const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const float* in = static_cast<const float*>(p.in);
+  const int slot = p.slot;  // multiple of 64 samples
+  const int cc_max = p.cc;
+  const int nstage = (p.nchans + cc_max - 1) / cc_max;
+  const unsigned row_bytes = static_cast<unsigned>(p.nsamp) * 4u;
+  // LDS byte offset of this lane's first sample in channel slot 0 of buffer 0
+  const unsigned lane_addr =
+      static_cast<unsigned>(reinterpret_cast<uintptr_t>(lds)) + static_cast<unsigned>(lane * K * 4);
+
+  // Copy the channels of stage `s` into LDS buffer `buf`; wavefront `wave`
+  // copies channels wave, wave+4, ... of the stage.
+  auto issue = [&](int s, int buf) {
+    const int c0 = s * cc_max;
+    const int ncc = min(cc_max, p.nchans - c0);
+    for (int i = wave; i < ncc; i += 4) {
+      const int c = c0 + i;
+      const int g0 = static_cast<int>(t0) + base[static_cast<int64_t>(dtile) * p.nchans + c];
+      __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(in + static_cast<int64_t>(c) * p.in_stride), 0,
+          static_cast<int>(row_bytes), 0x00020000);
+      float* dst = lds + (buf * cc_max + i) * slot;
+      for (int e = 0; e < slot; e += 64)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + e), 4,
+                                                 static_cast<unsigned>(g0 + e + lane) * 4u, 0, 0, 0);
+    }
+  };
+
+  float acc[DW * K];
+#pragma unroll
+  for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
+
+  issue(0, 0);
+  for (int s = 0; s < nstage; s++) {
+    const int buf = s & 1;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // stage s is in LDS; every wave is done with stage s-1
+    if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+    const int c0 = s * cc_max;
+    const int ncc = min(cc_max, p.nchans - c0);
+    for (int i = 0; i < ncc; i++) {
+      const int c = c0 + i;
+      const int32_t* rp = rel + (static_cast<int64_t>(dtile) * p.nchans + c) * TD + wave * DW;
+      int r[DW];
+#pragma unroll
+      for (int j = 0; j < DW; j++) r[j] = rp[j];
+      STEP(acc, r, lane_addr + static_cast<unsigned>((buf * cc_max + i) * slot * 4));
+    }
+  }
+  float* out = static_cast<float*>(p.out);
+#pragma unroll
+  for (int j = 0; j < DW; j++) {
+    const int row = p.rows[dtile * TD + wave * DW + j];
+    if (row < 0) continue;
+    float* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int64_t t = t0 + lane * K + k;
+      if (t < p.nout) o[t] = acc[j * K + k];
+    }
+  }
+}
+
 constexpr size_t kLdsBudget = 64 * 1024;   // per workgroup: two groups per CU
 constexpr size_t kLdsMax = 160 * 1024;
 
@@ -161,6 +257,49 @@ dd_status launch_lds(const TileShape& s, const TileTables& tt, const ExecArgs& a
   return DD_OK;
 }
 
+
+template <int DW, int K, int WMAX, int OCC, void (*STEP)(float*, const int*, unsigned)>
+dd_status launch_win_f32(const TileShape& s, const TileTables& tt, const ExecArgs& a,
+                         hipStream_t stream) {
+  constexpr int TT = 64 * K;
+  const int64_t n_ttiles = (a.nout + TT - 1) / TT;
+  const int64_t nblocks64 = n_ttiles * tt.ntiles;
+  if (nblocks64 > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many tiles");
+  if (a.nsamp >= (int64_t(1) << 29) || a.nout + tt.span_max >= (int64_t(1) << 29))
+    return set_error(DD_ERR_TOO_LARGE, "the window kernel addresses rows with 32-bit offsets");
+  const int slot = (TT + tt.span_max + WMAX + 63) & ~63;
+  const size_t slot_bytes = static_cast<size_t>(slot) * sizeof(float);
+  constexpr size_t kBudget = 160 * 1024 / OCC;  // OCC workgroups per CU, two buffers each
+  if (2 * slot_bytes > kBudget)
+    return set_error(DD_ERR_TOO_LARGE, "shift spread inside a DM tile does not fit LDS");
+  int cc = s.chans_per_stage;
+  while (cc > 1 && 2 * slot_bytes * cc > kBudget) cc--;
+  const size_t lds = 2 * slot_bytes * cc;
+  KParams p;
+  p.in = a.in;
+  p.in_stride = a.in_stride;
+  p.nsamp = a.nsamp;
+  p.out = a.out;
+  p.out_stride = a.out_stride;
+  p.nout = a.nout;
+  p.base = tt.d_base;
+  p.rel = tt.d_rel;
+  p.rows = tt.d_rows;
+  p.nchans = a.nchans;
+  p.slot = slot;
+  p.cc = cc;
+  p.n_dtiles = tt.ntiles;
+  p.nblocks = static_cast<int32_t>(nblocks64);
+  p.per_xcd = (p.nblocks + 7) / 8;
+  auto kern = k_dedisp_win_f32<DW, K, WMAX, OCC, STEP>;
+  if (lds > 64 * 1024)
+    DD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(8 * p.per_xcd), dim3(256), lds, stream, p, tt.d_rel, tt.d_base);
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
 }  // namespace
 
 bool dtype_pair_ok(dd_dtype in_t, dd_dtype out_t) {
@@ -192,6 +331,26 @@ TileShape default_shape(dd_dtype in_t, const dd_plan* plan) {
 
 dd_status launch_dedisperse(const TileShape& s, const TileTables& tt, dd_dtype in_t,
                             const ExecArgs& a, hipStream_t stream) {
+  if (s.variant == 1 && in_t == DD_F32 && s.waves == 4) {
+    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 20)
+      return launch_win_f32<8, 20, 56, 2, dd_f32_d8_k20_w56_channel>(s, tt, a, stream);
+    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 12)
+      return launch_win_f32<8, 12, 48, 3, dd_f32_d8_k12_w48_channel>(s, tt, a, stream);
+    if (s.dms_per_wave == 4 && s.tsamp_per_lane == 20)
+      return launch_win_f32<4, 20, 56, 3, dd_f32_d4_k20_w56_channel>(s, tt, a, stream);
+    if (s.dms_per_wave == 6 && s.tsamp_per_lane == 12)
+      return launch_win_f32<6, 12, 64, 3, dd_f32_d6_k12_w64_channel>(s, tt, a, stream);
+    if (s.dms_per_wave == 4 && s.tsamp_per_lane == 12)
+      return launch_win_f32<4, 12, 40, 4, dd_f32_d4_k12_w40_channel>(s, tt, a, stream);
+  }
+  if (s.variant == 2 && in_t == DD_F32 && s.waves == 4) {
+    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 20)
+      return launch_win_f32<8, 20, 56, 2, dd_jt_f32_d8_k20_w56_channel>(s, tt, a, stream);
+    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 12)
+      return launch_win_f32<8, 12, 48, 3, dd_jt_f32_d8_k12_w48_channel>(s, tt, a, stream);
+    if (s.dms_per_wave == 4 && s.tsamp_per_lane == 20)
+      return launch_win_f32<4, 20, 56, 3, dd_jt_f32_d4_k20_w56_channel>(s, tt, a, stream);
+  }
   if (s.variant == 0 && s.dms_per_wave == 8 && s.waves == 4 && s.tsamp_per_lane == 8) {
     switch (in_t) {
       case DD_F32: return launch_lds<float, float, 8, 8>(s, tt, a, stream);

@@ -5,6 +5,15 @@ namespace dd {
 
 TileShape shape_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp) {
   (void)nsamp;
+  if (in_t == DD_F32) {
+    TileShape s;
+    s.variant = 1;  // register-window kernel, three waves per SIMD
+    s.dms_per_wave = 8;
+    s.waves = 4;
+    s.tsamp_per_lane = 12;
+    s.chans_per_stage = 8;
+    return s;
+  }
   return default_shape(in_t, plan);
 }
 

@@ -169,3 +169,34 @@ def test_errors_from_execute():
     with pytest.raises(dd.DedispError) as ei:
         plan.execute(x, out=torch.zeros((2, 2000), dtype=torch.int32, device="cuda"))
     assert ei.value.status == dd.DD_ERR_DTYPE
+
+
+TILES_F32 = [
+    dict(variant=0, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8),
+    dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
+    dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=1, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
+    dict(variant=1, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=1, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
+    dict(variant=2, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
+    dict(variant=2, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=2, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
+]
+TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}".format(**t) for t in TILES_F32]
+
+
+@pytest.mark.parametrize("tile", TILES_F32, ids=TILE_IDS)
+@pytest.mark.parametrize("maxd", [0, 5, 60, 400])
+def test_f32_kernel_variants(tile, maxd):
+    """Every FP32 kernel variant, with shift spreads inside a wavefront from
+    none (all DMs share the window) to far beyond the register window (one
+    reload per DM)."""
+    g = np.random.default_rng(100 + maxd)
+    nchans, ndms, nsamp = 70, 75, 4000
+    tab = np.sort(rand_table(g, ndms, nchans, maxd), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, "f32", nchans, nsamp)
+    y = plan.execute_tiled(torch.from_numpy(x).cuda(), tile)
+    torch.cuda.synchronize()
+    e, _ = scaled_error(y.cpu().numpy(), x, tab)
+    assert e <= FP_TOL, e
