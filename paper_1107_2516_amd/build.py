@@ -22,7 +22,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
-          "-I", os.path.join(HERE, "..", "include")]
+          "-I", os.path.join(HERE, "..", "include"), "-I", BUILD]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 # host files whose floating-point results decide integers (the delay table)
@@ -51,10 +51,25 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def _generate(verbose: bool) -> None:
+    """Generated sources: the inline-assembly inner steps of the register-window
+    kernels (csrc/gen_window_asm.py -> _build/dd_window_asm.inc)."""
+    out = os.path.join(BUILD, "dd_window_asm.inc")
+    r = subprocess.run([sys.executable, os.path.join(CSRC, "gen_window_asm.py")],
+                       capture_output=True, text=True, check=True)
+    tmp = out + ".tmp"
+    with open(tmp, "w") as f:
+        f.write(r.stdout)
+    os.replace(tmp, out)
+    if verbose:
+        print(f"generated {out}", file=sys.stderr)
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
+    _generate(verbose)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
