@@ -60,6 +60,15 @@ typedef enum dd_dtype { DD_U8 = 1, DD_F16 = 2, DD_F32 = 3, DD_I32 = 4 } dd_dtype
 
 typedef struct dd_plan dd_plan;
 
+/* A kernel tile shape (see dd_tile_for, dd_execute_tiled, dd_autotune). */
+typedef struct dd_tile_config {
+  int32_t variant;      /* kernel variant index (implementation-defined) */
+  int32_t dms_per_wave; /* DM trials per wavefront */
+  int32_t waves;        /* wavefronts per workgroup */
+  int32_t tsamp_per_lane; /* output samples per lane */
+  int32_t chans_per_stage; /* channels staged in LDS per pipeline step */
+} dd_tile_config;
+
 /* ------------------------------------------------------------------------ */
 /* Plans                                                                    */
 /* ------------------------------------------------------------------------ */
@@ -147,19 +156,18 @@ dd_status dd_batch_update(dd_batch* batch, const dd_batch_item* items, int32_t n
 /* Enqueue the whole batch on `stream` (graph replay). */
 dd_status dd_batch_launch(dd_batch* batch, void* stream);
 
+/* Work items (beam, DM tile, time tile), persistent grid size and the tile
+ * shape of a batch; any output pointer may be NULL. */
+dd_status dd_batch_info(const dd_batch* batch, int32_t* work_items, int32_t* grid,
+                        dd_tile_config* cfg);
+
 dd_status dd_batch_destroy(dd_batch* batch);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuning                                                               */
 /* ------------------------------------------------------------------------ */
 
-typedef struct dd_tile_config {
-  int32_t variant;      /* kernel variant index (implementation-defined) */
-  int32_t dms_per_wave; /* DM trials per wavefront */
-  int32_t waves;        /* wavefronts per workgroup */
-  int32_t tsamp_per_lane; /* output samples per lane */
-  int32_t chans_per_stage; /* channels staged in LDS per pipeline step */
-} dd_tile_config;
+
 
 /*
  * Time the candidate tile shapes for (plan, in_t, nsamp) on `stream` using
@@ -180,6 +188,13 @@ dd_status dd_autotune(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, void* s
 dd_status dd_execute_tiled(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
                            int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
                            const dd_tile_config* cfg, void* stream);
+
+/*
+ * Time the candidate tile shapes on the batch itself (its output buffers are
+ * overwritten), keep the fastest for the batch and re-record its graph on
+ * the next launch.  Blocks until the timing is done.  best_ms may be NULL.
+ */
+dd_status dd_batch_autotune(dd_batch* batch, void* stream, dd_tile_config* best, float* best_ms);
 
 /* The tile shape dd_execute would use now for (plan, in_t, nsamp). */
 dd_status dd_tile_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, dd_tile_config* cfg);

@@ -92,6 +92,8 @@ _SIGS = {
     "dd_batch_update": [_P, _P, _I32],
     "dd_batch_launch": [_P, _P],
     "dd_batch_destroy": [_P],
+    "dd_batch_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(TileConfig)],
+    "dd_batch_autotune": [_P, _P, ctypes.POINTER(TileConfig), ctypes.POINTER(ctypes.c_float)],
     "dd_execute_tiled": [_P, _P, ctypes.c_int, _I64, _I64, _P, ctypes.c_int, _I64,
                          ctypes.POINTER(TileConfig), _P],
     "dd_autotune": [_P, ctypes.c_int, _I64, _P, ctypes.POINTER(TileConfig), ctypes.POINTER(ctypes.c_float)],
@@ -269,6 +271,82 @@ class Plan:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.dd_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many beams de-dispersed by one persistent, graph-captured launch.
+
+    beams: list of (plan, input tensor [nchans, nsamp], output tensor or None).
+    All inputs share one dtype.  Outputs are allocated when None.
+    """
+
+    def __init__(self, beams):
+        torch = _torch()
+        if not beams:
+            raise DedispError(DD_ERR_INVALID_ARG, "need at least one beam")
+        self.plans = [b[0] for b in beams]
+        self.inputs = [b[1] for b in beams]
+        self.outputs = []
+        for plan, x, o in beams:
+            if o is None:
+                o = torch.empty((plan.ndms, plan.nout(x.shape[1])), dtype=out_dtype_for(x.dtype),
+                                device=x.device)
+            self.outputs.append(o)
+        self.in_dtype = self.inputs[0].dtype
+        items = self._items()
+        h = ctypes.c_void_p()
+        _check(lib().dd_batch_create(items, len(items), dtype_code(self.in_dtype),
+                                     dtype_code(out_dtype_for(self.in_dtype)), ctypes.byref(h)))
+        self._h = h
+
+    def _items(self):
+        arr = (BatchItem * len(self.plans))()
+        for i, (p, x, o) in enumerate(zip(self.plans, self.inputs, self.outputs)):
+            if x.dtype != self.in_dtype:
+                raise DedispError(DD_ERR_DTYPE, "all beams of a batch share one input dtype")
+            if x.dim() != 2 or x.stride(1) != 1 or x.shape[0] != p.nchans:
+                raise DedispError(DD_ERR_INVALID_ARG, "beam input must be [nchans, nsamp]")
+            if o.dim() != 2 or o.stride(1) != 1 or o.shape[0] != p.ndms:
+                raise DedispError(DD_ERR_INVALID_ARG, "beam output must be [ndms, nout]")
+            arr[i] = BatchItem(p.handle.value if isinstance(p.handle, ctypes.c_void_p) else p.handle,
+                               x.data_ptr(), x.shape[1], x.stride(0), o.data_ptr(), o.stride(0))
+        return arr
+
+    def update(self, inputs=None, outputs=None):
+        """Point the batch at new tensors of the same shapes and strides."""
+        if inputs is not None:
+            self.inputs = list(inputs)
+        if outputs is not None:
+            self.outputs = list(outputs)
+        items = self._items()
+        _check(lib().dd_batch_update(self._h, items, len(items)))
+
+    def launch(self, stream=None):
+        _check(lib().dd_batch_launch(self._h, stream_handle(stream)))
+        return self.outputs
+
+    def info(self):
+        n, g, cfg = _I32(), _I32(), TileConfig()
+        _check(lib().dd_batch_info(self._h, ctypes.byref(n), ctypes.byref(g), ctypes.byref(cfg)))
+        return {"work_items": n.value, "grid": g.value, "tile": cfg.as_dict()}
+
+    def autotune(self, stream=None):
+        cfg, ms = TileConfig(), ctypes.c_float()
+        _check(lib().dd_batch_autotune(self._h, stream_handle(stream), ctypes.byref(cfg),
+                                       ctypes.byref(ms)))
+        return cfg.as_dict(), ms.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_batch_destroy(h)
         self._h = None
 
     def __del__(self):

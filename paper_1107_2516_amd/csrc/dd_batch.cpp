@@ -1,15 +1,270 @@
-// Batched many-beam execution.
+// Batches: many beams (each with its own plan, input and output) processed by
+// one persistent kernel launch.  The launch (counter reset kernel + persistent
+// kernel) is recorded into a HIP graph on first use and replayed afterwards;
+// dd_batch_update rewrites the device descriptor table in place, so new
+// buffers of the same shapes need no re-capture.
+#include <algorithm>
+#include <cstring>
+
 #include "dd_internal.h"
 
+struct dd_batch {
+  dd_dtype in_t = DD_F32, out_t = DD_F32;
+  std::vector<dd_batch_item> items;
+  dd::TileShape shape;
+  dd::BatchLaunch bl;
+  int device = 0;
+  void* d_params = nullptr;
+  int32_t* d_first = nullptr;
+  unsigned* d_counters = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::mutex mu;
+  ~dd_batch();
+};
+
+namespace dd {
+
+namespace {
+
+dd_status validate_items(const dd_batch_item* items, int32_t n, dd_dtype in_t, dd_dtype out_t) {
+  if (!items || n < 1) return set_error(DD_ERR_INVALID_ARG, "need at least one batch item");
+  if (!dtype_pair_ok(in_t, out_t))
+    return set_error(DD_ERR_DTYPE, "supported pairs: f32->f32, f16->f32, u8->i32");
+  for (int32_t i = 0; i < n; i++) {
+    const dd_batch_item& it = items[i];
+    if (!it.plan || !it.d_in || !it.d_out)
+      return set_error(DD_ERR_INVALID_ARG, "batch item with a NULL plan or buffer");
+    if (it.nsamp <= it.plan->max_shift)
+      return set_error(DD_ERR_NSAMP, "batch item nsamp must exceed its plan's max_shift");
+    if (it.in_stride < it.nsamp || it.out_stride < it.nsamp - it.plan->max_shift)
+      return set_error(DD_ERR_INVALID_ARG, "batch item stride smaller than its row length");
+  }
+  return DD_OK;
+}
+
+std::vector<ExecArgs> exec_args(const std::vector<dd_batch_item>& items) {
+  std::vector<ExecArgs> a(items.size());
+  for (size_t i = 0; i < items.size(); i++) {
+    const dd_batch_item& it = items[i];
+    dd_plan* plan = const_cast<dd_plan*>(it.plan);
+    a[i] = ExecArgs{plan, it.d_in, it.nsamp, it.in_stride, it.d_out, it.out_stride,
+                    it.nsamp - plan->max_shift, plan->nchans};
+  }
+  return a;
+}
+
+void drop_graph(dd_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// (Re)build the launch for shape s and upload its descriptor table.
+dd_status configure(dd_batch* b, const TileShape& s) {
+  BatchLaunch bl;
+  std::vector<ExecArgs> a = exec_args(b->items);
+  dd_status st = batch_prepare(s, b->in_t, a.data(), static_cast<int>(a.size()), &bl);
+  if (st != DD_OK) return st;
+  if (!b->d_params) {
+    DD_HIP(hipMalloc(&b->d_params, bl.params.size()));
+    DD_HIP(hipMalloc(&b->d_first, bl.first_item.size() * sizeof(int32_t)));
+    DD_HIP(hipMalloc(&b->d_counters, 64 * sizeof(unsigned)));
+  }
+  DD_HIP(hipMemcpy(b->d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice));
+  DD_HIP(hipMemcpy(b->d_first, bl.first_item.data(), bl.first_item.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+  drop_graph(b);
+  b->bl = std::move(bl);
+  b->shape = s;
+  return DD_OK;
+}
+
+dd_status capture(dd_batch* b) {
+  if (!b->cap_stream) DD_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  DD_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  dd_status st = batch_enqueue(b->bl, b->d_params, b->d_first, b->d_counters, b->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (st != DD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+  b->graph = g;
+  DD_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return DD_OK;
+}
+
+}  // namespace
+
+// Timing hook for the autotuner: enqueue the batch with shape s, uncaptured.
+dd_status batch_time_shape(dd_batch* b, const TileShape& s, hipStream_t stream, int reps,
+                           float* ms) {
+  BatchLaunch bl;
+  std::vector<ExecArgs> a = exec_args(b->items);
+  dd_status st = batch_prepare(s, b->in_t, a.data(), static_cast<int>(a.size()), &bl);
+  if (st != DD_OK) return st;
+  void* d_params = nullptr;
+  int32_t* d_first = nullptr;
+  DD_HIP(hipMalloc(&d_params, bl.params.size()));
+  hipError_t e = hipMalloc(&d_first, bl.first_item.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(d_first, bl.first_item.data(), bl.first_item.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    st = batch_enqueue(bl, d_params, d_first, b->d_counters, stream);  // warm-up
+    if (st == DD_OK) e = hipEventRecord(e0, stream);
+    for (int r = 0; st == DD_OK && e == hipSuccess && r < reps; r++)
+      st = batch_enqueue(bl, d_params, d_first, b->d_counters, stream);
+    if (st == DD_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (st == DD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    if (st == DD_OK && e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (st == DD_OK && e == hipSuccess) *ms /= static_cast<float>(reps);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(d_params);
+  (void)hipFree(d_first);
+  if (st != DD_OK) return st;
+  if (e != hipSuccess) return hip_error(e, "timing a batch shape");
+  return DD_OK;
+}
+
+dd_dtype batch_in_type(const dd_batch* b) { return b->in_t; }
+
+dd_status batch_set_shape(dd_batch* b, const TileShape& s) {
+  std::lock_guard<std::mutex> lk(b->mu);
+  return configure(b, s);
+}
+
+}  // namespace dd
+
+dd_batch::~dd_batch() {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  dd::drop_graph(this);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  (void)hipFree(d_params);
+  (void)hipFree(d_first);
+  (void)hipFree(d_counters);
+  (void)hipSetDevice(cur);
+}
+
 extern "C" {
-dd_status dd_batch_create(const dd_batch_item*, int32_t, dd_dtype, dd_dtype, dd_batch**) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "batching not built yet");
+
+dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, dd_dtype out_t,
+                          dd_batch** out) {
+  try {
+    if (!out) return dd::set_error(DD_ERR_INVALID_ARG, "out is NULL");
+    dd_status st = dd::validate_items(items, n, in_t, out_t);
+    if (st != DD_OK) return st;
+    std::unique_ptr<dd_batch> b(new dd_batch());
+    b->in_t = in_t;
+    b->out_t = out_t;
+    b->items.assign(items, items + n);
+    DD_HIP(hipGetDevice(&b->device));
+    // one tile shape for the whole batch: the tuned (or default) shape of the
+    // largest beam, else the LDS-streaming kernel when a beam does not suit it
+    size_t big = 0;
+    for (int32_t i = 1; i < n; i++)
+      if (static_cast<double>(items[i].nsamp) * items[i].plan->ndms * items[i].plan->nchans >
+          static_cast<double>(items[big].nsamp) * items[big].plan->ndms * items[big].plan->nchans)
+        big = static_cast<size_t>(i);
+    dd::TileShape s = dd::shape_for(items[big].plan, in_t, items[big].nsamp);
+    st = dd::configure(b.get(), s);
+    if (st == DD_ERR_TOO_LARGE && s.variant != 0) st = dd::configure(b.get(), dd::default_shape(in_t, items[0].plan));
+    if (st != DD_OK) return st;
+    *out = b.release();
+    return DD_OK;
+  } catch (const std::bad_alloc&) {
+    return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
 }
-dd_status dd_batch_update(dd_batch*, const dd_batch_item*, int32_t) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "batching not built yet");
+
+dd_status dd_batch_update(dd_batch* b, const dd_batch_item* items, int32_t n) {
+  try {
+    if (!b) return dd::set_error(DD_ERR_INVALID_ARG, "batch is NULL");
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (n != static_cast<int32_t>(b->items.size()))
+      return dd::set_error(DD_ERR_INVALID_ARG, "a batch update must keep the number of items");
+    dd_status st = dd::validate_items(items, n, b->in_t, b->out_t);
+    if (st != DD_OK) return st;
+    for (int32_t i = 0; i < n; i++) {
+      const dd_batch_item& o = b->items[i];
+      const dd_batch_item& it = items[i];
+      if (o.plan != it.plan || o.nsamp != it.nsamp || o.in_stride != it.in_stride ||
+          o.out_stride != it.out_stride)
+        return dd::set_error(DD_ERR_INVALID_ARG,
+                             "a batch update may change buffers only, not plans, sizes or strides");
+    }
+    std::vector<dd_batch_item> keep = b->items;
+    b->items.assign(items, items + n);
+    dd::BatchLaunch bl;
+    std::vector<dd::ExecArgs> a = dd::exec_args(b->items);
+    st = dd::batch_prepare(b->shape, b->in_t, a.data(), n, &bl);
+    if (st != DD_OK) {
+      b->items = keep;
+      return st;
+    }
+    if (bl.params.size() != b->bl.params.size() || bl.total != b->bl.total) {
+      b->items = keep;
+      return dd::set_error(DD_ERR_STATE, "batch layout changed unexpectedly");
+    }
+    // same layout: only the pointers change; the captured graph reads the table
+    DD_HIP(hipMemcpy(b->d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice));
+    b->bl.params = std::move(bl.params);
+    return DD_OK;
+  } catch (const std::bad_alloc&) {
+    return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
 }
-dd_status dd_batch_launch(dd_batch*, void*) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "batching not built yet");
+
+dd_status dd_batch_launch(dd_batch* b, void* stream) {
+  try {
+    if (!b) return dd::set_error(DD_ERR_INVALID_ARG, "batch is NULL");
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (!b->exec) {
+      dd_status st = dd::capture(b);
+      if (st != DD_OK) return st;
+    }
+    DD_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    return DD_OK;
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
 }
-dd_status dd_batch_destroy(dd_batch*) { return DD_OK; }
+
+dd_status dd_batch_info(const dd_batch* b, int32_t* work_items, int32_t* grid,
+                        dd_tile_config* cfg) {
+  if (!b) return dd::set_error(DD_ERR_INVALID_ARG, "batch is NULL");
+  if (work_items) *work_items = b->bl.total;
+  if (grid) *grid = b->bl.grid;
+  if (cfg) {
+    cfg->variant = b->shape.variant;
+    cfg->dms_per_wave = b->shape.dms_per_wave;
+    cfg->waves = b->shape.waves;
+    cfg->tsamp_per_lane = b->shape.tsamp_per_lane;
+    cfg->chans_per_stage = b->shape.chans_per_stage;
+  }
+  return DD_OK;
 }
+
+dd_status dd_batch_destroy(dd_batch* b) {
+  delete b;
+  return DD_OK;
+}
+
+}  // extern "C"

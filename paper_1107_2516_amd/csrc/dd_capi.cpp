@@ -94,17 +94,13 @@ dd_status execute_common(const dd_plan* cplan, const void* d_in, dd_dtype in_t, 
   dd::TileShape s = forced ? *forced : dd::shape_for(plan, in_t, nsamp);
   if (s.dms_per_wave < 1 || s.waves < 1 || s.tsamp_per_lane < 1 || s.chans_per_stage < 1)
     return dd::set_error(DD_ERR_INVALID_ARG, "tile shape fields must be >= 1");
-  dd::ExecArgs a{d_in, nsamp, in_stride, d_out, out_stride, nout, plan->nchans};
-  const dd::TileTables* tt = nullptr;
-  dd_status st = dd::plan_tiles(plan, s.dms_per_tile(), &tt);
-  if (st != DD_OK) return st;
-  st = dd::launch_dedisperse(s, *tt, in_t, a, static_cast<hipStream_t>(stream));
+  dd::ExecArgs a{plan, d_in, nsamp, in_stride, d_out, out_stride, nout, plan->nchans};
+  dd_status st = dd::launch_dedisperse(s, in_t, a, static_cast<hipStream_t>(stream));
   if (st == DD_ERR_TOO_LARGE && !forced && s.variant != 0) {
-    // the shift spread of this plan does not fit the fast variant's staging
+    // the plan's shift spread or the row alignment does not suit the fast
+    // variant: use the LDS-streaming kernel
     s = dd::default_shape(in_t, plan);
-    st = dd::plan_tiles(plan, s.dms_per_tile(), &tt);
-    if (st != DD_OK) return st;
-    st = dd::launch_dedisperse(s, *tt, in_t, a, static_cast<hipStream_t>(stream));
+    st = dd::launch_dedisperse(s, in_t, a, static_cast<hipStream_t>(stream));
   }
   return st;
 }

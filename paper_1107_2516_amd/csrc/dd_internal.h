@@ -63,6 +63,8 @@ struct TileTables {
 
 struct DeviceTables {
   std::map<int, TileTables> by_td;
+  // aligned-copies offsets keyed by (td, samples per dword, dwords per copy)
+  std::map<std::tuple<int, int, int>, int32_t*> aoff;
 };
 
 }  // namespace dd
@@ -87,9 +89,14 @@ dd_status plan_from_table(int32_t nchans, int32_t ndms, const int32_t* delays, d
 
 // Uploads (once per device) and returns the tile tables for height td.
 dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out);
+// Per (tile, channel, DM) dword offsets for the aligned-copies kernels: with
+// a = base & (epd-1) and R = a + rel, the DM reads copy R mod epd at dword
+// R / epd, i.e. offset (R mod epd) * slotd + R / epd within the channel.
+dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** out);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {
+  dd_plan* plan;
   const void* in;
   int64_t nsamp, in_stride;
   void* out;
@@ -99,8 +106,24 @@ struct ExecArgs {
 bool dtype_pair_ok(dd_dtype in_t, dd_dtype out_t);
 size_t dtype_size(dd_dtype t);
 TileShape default_shape(dd_dtype in_t, const dd_plan* plan);
-dd_status launch_dedisperse(const TileShape& shape, const TileTables& tt, dd_dtype in_t,
-                            const ExecArgs& a, hipStream_t stream);
+bool shape_supported(const TileShape& s, dd_dtype in_t);
+dd_status launch_dedisperse(const TileShape& shape, dd_dtype in_t, const ExecArgs& a,
+                            hipStream_t stream);
+
+// A prepared persistent multi-beam launch (host side).
+struct BatchLaunch {
+  std::vector<unsigned char> params;  // per-beam kernel parameters, copied to the device
+  std::vector<int32_t> first_item;    // prefix sums of work items, nbeams + 1
+  int32_t total = 0;                  // work items
+  size_t lds = 0;                     // dynamic LDS per workgroup (max over beams)
+  const void* kernel = nullptr;
+  int grid = 0;                       // persistent grid: CUs x resident workgroups per CU
+};
+dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
+                        BatchLaunch* out);
+// Zero the 8 work counters and launch the persistent kernel on `stream`.
+dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
+                        unsigned* d_counters, hipStream_t stream);
 
 // Tile-shape selection (dd_tune.cpp).
 TileShape shape_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp);

@@ -1,32 +1,103 @@
 // De-dispersion kernels for gfx950 (section 3.1, brute force):
 //     out[d][t] = sum over c of in[c][t + delay[d][c]]
 //
-// Design (plain LDS-staged gather-add; no MFMA: the work is a gather and a
-// sum, not a contraction):
-//  * A workgroup of 4 wavefronts owns a DM tile (4*DW trial DMs with similar
-//    shifts) and a time tile of 64*K output samples.  Lane l of a wavefront
-//    owns samples t0 + l + 64k, k < K, for the wavefront's DW DMs, so every
-//    LDS read and every global store of a wavefront touches 64 consecutive
-//    elements.
-//  * Channels are streamed in stages of `cc` channels.  For each staged
-//    channel the workgroup copies one contiguous window of the input,
-//    [t0 + base_c, t0 + base_c + slot), into LDS with coalesced loads; base_c
-//    is the smallest shift of channel c in the DM tile, and the window covers
-//    the time tile plus the largest in-tile shift difference.  Every DM of
-//    the tile then reads its shifted samples from that window: one HBM/L2
-//    read feeds 4*DW DMs.
-//  * Shift differences come from a per-tile table with wave-uniform indices,
-//    so they are read with scalar loads.
-//  * Blocks are renumbered so that each of the 8 XCDs (block b runs on XCD
-//    b mod 8) works through a contiguous range of (time tile, DM tile) items
-//    with the DM tile varying fastest: the DM tiles of one time tile share
-//    their input windows through that XCD's L2.
+// No MFMA: the work is a data-dependent gather and a sum, not a contraction.
+//
+// Common structure.  A workgroup of 4 wavefronts owns a DM tile (TD trial DMs
+// with similar shifts, grouped on the host) and a time tile of TT output
+// samples.  Channels are streamed through LDS in stages: for each staged
+// channel the workgroup copies one contiguous window of the input,
+// [t0 + base_c, t0 + base_c + slot), base_c being the smallest shift of
+// channel c in the tile; every DM of the tile then reads its shifted samples
+// from that window, so one L2/HBM read of a sample feeds TD DMs.  The
+// per-(tile, channel, DM) shift differences come from host tables read with
+// scalar loads.
+//
+// Each variant is a per-tile device body.  It runs either from a plain grid
+// (one workgroup per tile, XCD-aware numbering: block b runs on XCD b mod 8,
+// so each XCD walks a contiguous range of (time tile, DM tile) items with the
+// DM tile fastest and the DM tiles of one time tile share input windows in
+// that XCD's L2) or from the persistent multi-beam kernel (k_batch), whose
+// fixed grid pulls (beam, DM tile, time tile) items from per-XCD counters.
+//
+// Variants:
+//  0  BodyLds:     lane l owns samples t0 + l + 64k; one LDS read per add.
+//  1  BodyWin:     FP32; lane owns K consecutive samples; a register window
+//                  per channel serves all DMs of the wavefront through
+//                  VGPR-relative adds (generated asm, dd_window_asm.inc).
+//  2  BodyWin:     same, jump-table flavour of the asm step.
+//  3  BodyCopies:  u8 / f16; EPD shifted copies of each staged channel so
+//                  every DM reads aligned dwords; u8 sums in 16-bit SWAR
+//                  lanes with fast VOP2 instructions, f16 with v_fma_mix.
+#include <cstring>
+#include <type_traits>
+
 #include "dd_internal.h"
 
 namespace dd {
 namespace {
 
 #include "dd_window_asm.inc"
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef int int4v __attribute__((ext_vector_type(4)));
+typedef int int8v __attribute__((ext_vector_type(8)));
+
+struct KParams {
+  const void* in;
+  int64_t in_stride, nsamp;
+  void* out;
+  int64_t out_stride, nout;
+  const int32_t* base;  // [tile][nchans]
+  const int32_t* tab;   // rel (variants 0-2) or copy offsets (variant 3), [tile][nchans][TD]
+  const int32_t* rows;  // [tile][TD]
+  int32_t nchans, slot, cc;
+  int32_t n_dtiles, n_ttiles, nblocks, per_xcd;
+};
+
+// Wave-uniform loads through the scalar cache.  The tables are read-only for
+// the whole launch; the explicit s_load keeps them out of the vector memory
+// path even where the compiler cannot prove that no store aliases them.
+__device__ __forceinline__ int sload1(const int32_t* p) {
+  int v;
+  asm volatile("s_load_dword %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+  return v;
+}
+template <int N>
+__device__ __forceinline__ void sload(const int32_t* p, int* r) {
+  static_assert(N == 4 || N == 8, "4 or 8 dwords");
+  if constexpr (N == 4) {
+    int4v v;
+    asm volatile("s_load_dwordx4 %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+#pragma unroll
+    for (int i = 0; i < 4; i++) r[i] = v[i];
+  } else {
+    int8v v;
+    asm volatile("s_load_dwordx8 %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+#pragma unroll
+    for (int i = 0; i < 8; i++) r[i] = v[i];
+  }
+}
+// DW consecutive table entries (the tables are padded so that the
+// power-of-two over-read of the last wavefront stays inside them).
+template <int DW>
+__device__ __forceinline__ void sload_dw(const int32_t* p, int* r) {
+  if constexpr (DW <= 4) {
+    int t[4];
+    sload<4>(p, t);
+#pragma unroll
+    for (int i = 0; i < DW; i++) r[i] = t[i];
+  } else {
+    int t[8];
+    sload<8>(p, t);
+#pragma unroll
+    for (int i = 0; i < DW; i++) r[i] = t[i];
+  }
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// ------------------------------------------------------------------ variant 0
 
 template <typename T>
 struct Acc;
@@ -46,257 +117,560 @@ struct Acc<uint8_t> {
   __device__ static uint32_t load(uint8_t x) { return x; }
 };
 
-struct KParams {
-  const void* in;
-  int64_t in_stride, nsamp;
-  void* out;
-  int64_t out_stride, nout;
-  const int32_t* base;
-  const int32_t* rel;
-  const int32_t* rows;
-  int32_t nchans, slot, cc;
-  int32_t n_dtiles, nblocks, per_xcd;
+template <typename Tin, typename Tout, int DW, int K>
+struct BodyLds {
+  static constexpr int TD = 4 * DW, TT = 64 * K, OCC = 2;
+  __device__ static void run(const KParams& p, int dtile, int ttile) {
+    using TA = typename Acc<Tin>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Tin* lds = reinterpret_cast<Tin*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_id();
+    const Tin* in = static_cast<const Tin*>(p.in);
+    TA acc[DW][K];
+#pragma unroll
+    for (int d = 0; d < DW; d++)
+#pragma unroll
+      for (int k = 0; k < K; k++) acc[d][k] = TA(0);
+    for (int c0 = 0; c0 < p.nchans; c0 += p.cc) {
+      const int ncc = min(p.cc, p.nchans - c0);
+      __syncthreads();
+      for (int cc = 0; cc < ncc; cc++) {
+        const int c = c0 + cc;
+        const int64_t g0 = t0 + sload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c);
+        const Tin* src = in + static_cast<int64_t>(c) * p.in_stride;
+        Tin* dst = lds + cc * p.slot;
+        for (int j = tid; j < p.slot; j += 256) {
+          const int64_t g = g0 + j;
+          dst[j] = g < p.nsamp ? src[g] : Tin(0);
+        }
+      }
+      __syncthreads();
+      for (int cc = 0; cc < ncc; cc++) {
+        const int c = c0 + cc;
+        int r[DW];
+        sload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c) * TD + wave * DW, r);
+        const Tin* row = lds + cc * p.slot + lane;
+#pragma unroll
+        for (int d = 0; d < DW; d++) {
+#pragma unroll
+          for (int k = 0; k < K; k++) acc[d][k] += Acc<Tin>::load(row[r[d] + 64 * k]);
+        }
+      }
+    }
+    Tout* out = static_cast<Tout*>(p.out);
+#pragma unroll
+    for (int d = 0; d < DW; d++) {
+      const int row = p.rows[dtile * TD + wave * DW + d];
+      if (row < 0) continue;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int64_t t = t0 + lane + 64 * k;
+        if (t < p.nout)
+          out[static_cast<int64_t>(row) * p.out_stride + t] = static_cast<Tout>(acc[d][k]);
+      }
+    }
+  }
+  // LDS and launch geometry for one plan/beam; 0 on success
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    int s = (TT + span_max + 15) & ~15;
+    const size_t sb = static_cast<size_t>(s) * sizeof(Tin);
+    if (sb > 160 * 1024) return -1;
+    int c = cc_req;
+    while (c > 1 && sb * c > 64 * 1024) c--;
+    *slot = s;
+    *cc = c;
+    *lds = sb * c;
+    return 0;
+  }
+  static constexpr int table_epd = 0;  // uses rel
 };
 
-template <typename Tin, typename Tout, int DW, int K>
-__global__ __launch_bounds__(256) void k_dedisp_lds(KParams p) {
-  using TA = typename Acc<Tin>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
-  Tin* lds = reinterpret_cast<Tin*>(smem);
-  constexpr int TD = 4 * DW, TT = 64 * K;
-  const int b = blockIdx.x;
-  const int w = (b & 7) * p.per_xcd + (b >> 3);
-  if (w >= p.nblocks) return;
-  const int dtile = w % p.n_dtiles;
-  const int ttile = w / p.n_dtiles;
-  const int64_t t0 = static_cast<int64_t>(ttile) * TT;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const Tin* in = static_cast<const Tin*>(p.in);
-
-  TA acc[DW][K];
-#pragma unroll
-  for (int d = 0; d < DW; d++)
-#pragma unroll
-    for (int k = 0; k < K; k++) acc[d][k] = TA(0);
-
-  for (int c0 = 0; c0 < p.nchans; c0 += p.cc) {
-    const int ncc = min(p.cc, p.nchans - c0);
-    __syncthreads();
-    for (int cc = 0; cc < ncc; cc++) {
-      const int c = c0 + cc;
-      const int64_t g0 = t0 + p.base[static_cast<int64_t>(dtile) * p.nchans + c];
-      const Tin* src = in + static_cast<int64_t>(c) * p.in_stride;
-      Tin* dst = lds + cc * p.slot;
-      for (int j = tid; j < p.slot; j += 256) {
-        const int64_t g = g0 + j;
-        dst[j] = g < p.nsamp ? src[g] : Tin(0);
-      }
-    }
-    __syncthreads();
-    for (int cc = 0; cc < ncc; cc++) {
-      const int c = c0 + cc;
-      const int32_t* r = p.rel + (static_cast<int64_t>(dtile) * p.nchans + c) * TD + wave * DW;
-      const Tin* row = lds + cc * p.slot + lane;
-#pragma unroll
-      for (int d = 0; d < DW; d++) {
-        const int off = r[d];
-#pragma unroll
-        for (int k = 0; k < K; k++) acc[d][k] += Acc<Tin>::load(row[off + 64 * k]);
-      }
-    }
-  }
-  Tout* out = static_cast<Tout*>(p.out);
-#pragma unroll
-  for (int d = 0; d < DW; d++) {
-    const int row = p.rows[dtile * TD + wave * DW + d];
-    if (row < 0) continue;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-      const int64_t t = t0 + lane + 64 * k;
-      if (t < p.nout) out[static_cast<int64_t>(row) * p.out_stride + t] = static_cast<Tout>(acc[d][k]);
-    }
-  }
-}
-
-
-// Register-window variant for FP32 input.  Same tiling as k_dedisp_lds, but
-// lane l owns K *consecutive* samples t0 + l*K + k, so the samples a lane
-// needs for all DMs of its wavefront at one channel are a few overlapping
-// K-long runs of the staged window.  STEP (generated inline assembly,
-// dd_window_asm.inc) loads a register window once and serves every DM whose
-// run fits in it through VGPR-relative addressing.  K is 4 mod 8 so the
-// 16-byte window reads of 64 lanes (stride 4K bytes) hit distinct LDS banks.
+// -------------------------------------------------------------- variants 1, 2
+//
+// Register-window variant for FP32 input.  Lane l owns K *consecutive*
+// samples t0 + l*K + k, so the samples a lane needs for all DMs of its
+// wavefront at one channel are a few overlapping K-long runs of the staged
+// window.  STEP loads a register window once and serves every DM whose run
+// fits in it.  K is 4 mod 8 so the 16-byte window reads of 64 lanes (stride
+// 4K bytes) hit distinct LDS banks.
 //
 // Staging is asynchronous and double-buffered: the channels of stage s+1 are
 // copied global -> LDS by buffer loads that write LDS directly (no VGPRs),
 // issued before stage s is computed.  The buffer descriptor of each channel
 // row bounds reads at nsamp samples, so samples past the end read as zero
 // (they only feed outputs t >= nout, which are not stored).
-typedef __attribute__((address_space(3))) void lds_void_t;
+template <int DW, int K, int WMAX, int OCC_, void (*STEP)(float*, const int*, unsigned)>
+struct BodyWin {
+  static constexpr int TD = 4 * DW, TT = 64 * K, OCC = OCC_;
+  __device__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* lds = reinterpret_cast<float*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_id();
+    const float* in = static_cast<const float*>(p.in);
+    const int slot = p.slot;  // multiple of 64 samples
+    const int cc_max = p.cc;
+    const int nstage = (p.nchans + cc_max - 1) / cc_max;
+    const unsigned row_bytes = static_cast<unsigned>(p.nsamp) * 4u;
+    const unsigned lane_addr = static_cast<unsigned>(reinterpret_cast<uintptr_t>(lds)) +
+                               static_cast<unsigned>(lane * K * 4);
+    auto issue = [&](int s, int buf) {
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int g0 =
+            static_cast<int>(t0) + sload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c);
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(in + static_cast<int64_t>(c) * p.in_stride), 0,
+            static_cast<int>(row_bytes), 0x00020000);
+        float* dst = lds + (buf * cc_max + i) * slot;
+        for (int e = 0; e < slot; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(g0 + e + lane) * 4u, 0, 0, 0);
+      }
+    };
+    float acc[DW * K];
+#pragma unroll
+    for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
+    issue(0, 0);
+    for (int s = 0; s < nstage; s++) {
+      const int buf = s & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // stage s is in LDS; every wave is done with stage s-1
+      if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = 0; i < ncc; i++) {
+        int r[DW];
+        sload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0 + i) * TD + wave * DW, r);
+        STEP(acc, r, lane_addr + static_cast<unsigned>((buf * cc_max + i) * slot * 4));
+      }
+    }
+    float* out = static_cast<float*>(p.out);
+#pragma unroll
+    for (int j = 0; j < DW; j++) {
+      const int row = p.rows[dtile * TD + wave * DW + j];
+      if (row < 0) continue;
+      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int64_t t = t0 + lane * K + k;
+        if (t < p.nout) o[t] = acc[j * K + k];
+      }
+    }
+  }
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    const int s = (TT + span_max + WMAX + 63) & ~63;
+    const size_t sb = static_cast<size_t>(s) * sizeof(float);
+    const size_t budget = 160 * 1024 / OCC;
+    if (2 * sb > budget) return -1;
+    int c = cc_req;
+    while (c > 1 && 2 * sb * c > budget) c--;
+    *slot = s;
+    *cc = c;
+    *lds = 2 * sb * c;
+    return 0;
+  }
+  static constexpr int table_epd = 0;
+};
 
-template <int DW, int K, int WMAX, int OCC, void (*STEP)(float*, const int*, unsigned)>
-__global__ __launch_bounds__(256, OCC) void k_dedisp_win_f32(KParams p,
-                                                           const int32_t* __restrict__ rel,
-                                                           const int32_t* __restrict__ base) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  float* lds = reinterpret_cast<float*>(smem);
-  constexpr int TD = 4 * DW, TT = 64 * K;
+// ---------------------------------------------------------------- variant 3
+//
+// Aligned-copies variant for 8-bit and half-precision input.  A dword holds
+// EPD samples (4 u8 or 2 f16).  Lane l owns the EPD samples of dwords
+// l + 64i, i < I, of the time tile, for the DW DMs of its wavefront.  A DM
+// whose shift is not a multiple of EPD would need every dword realigned;
+// instead the workgroup keeps EPD copies of each staged channel, copy m
+// shifted by m samples, so every DM reads whole aligned dwords
+// (ds_read2st64_b32, 64 consecutive dwords per wavefront).  Copy 0 is written
+// by asynchronous buffer loads straight into LDS; copies 1..EPD-1 are built
+// from it with v_alignbyte_b32 once it lands; both are double-buffered by
+// stage.  The dword offset of every (tile, channel, DM) within the channel's
+// copies is precomputed on the host (plan_aoff), so the per-DM work in the
+// loop is one address add and the reads.
+//
+// Accumulation:
+//  * u8: SWAR in fast VOP2 instructions: e = x & 0x00ff00ff and
+//    o = (x >> 8) & 0x00ff00ff each hold two samples in 16-bit lanes and are
+//    added into 16-bit-lane accumulators, flushed into 32-bit sums every 256
+//    channels (255 * 256 < 2^16, so no lane ever carries).
+//  * f16: v_fma_mix_f32 (x * 1.0 + acc with x an f16 half; the product is
+//    exact), one instruction per sample, FP32 accumulation.
+template <typename Tin, int DW, int I, int OCC_>
+struct BodyCopies {
+  static constexpr int EPD = 4 / static_cast<int>(sizeof(Tin));
+  static constexpr int SH = EPD == 4 ? 2 : 1;
+  static constexpr int TD = 4 * DW, TT = 64 * I * EPD, OCC = OCC_;
+  __device__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* lds = reinterpret_cast<uint32_t*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_id();
+    const unsigned char* in = static_cast<const unsigned char*>(p.in);
+    const int slotd = p.slot;  // dwords per copy per channel, multiple of 64
+    const int cc_max = p.cc;
+    const int nstage = (p.nchans + cc_max - 1) / cc_max;
+    const int64_t row_bytes = p.in_stride * static_cast<int64_t>(sizeof(Tin));
+    const int full_dwords = static_cast<int>(p.nsamp / EPD);  // dwords wholly inside a row
+    const int tail = static_cast<int>(p.nsamp % EPD);         // samples in the partial dword
+    const int chan_dw = EPD * slotd;  // LDS: [buffer][stage channel][copy][slotd]
+    auto window_dword = [&](int c) -> int {
+      return static_cast<int>(
+          (t0 + sload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
+    };
+    auto issue = [&](int s, int buf) {
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int gd = window_dword(c);
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char*>(in + static_cast<int64_t>(c) * row_bytes), 0,
+            full_dwords * 4, 0x00020000);
+        uint32_t* dst = lds + (buf * cc_max + i) * chan_dw;
+        for (int e = 0; e < slotd; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
+      }
+    };
+    // The partial dword at the end of row c, assembled from bytes (the buffer
+    // loads read only whole dwords and leave it at zero).
+    auto tail_dword = [&](int c) -> uint32_t {
+      const unsigned char* row =
+          in + static_cast<int64_t>(c) * row_bytes + static_cast<int64_t>(full_dwords) * 4;
+      uint32_t v = 0;
+      for (int k = 0; k < tail * static_cast<int>(sizeof(Tin)); k++)
+        v |= static_cast<uint32_t>(row[k]) << (8 * k);
+      return v;
+    };
+    auto build = [&](int s, int buf) {
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = 0; i < ncc; i++) {
+        const int c = c0 + i;
+        uint32_t* d0 = lds + (buf * cc_max + i) * chan_dw;
+        const int tl = full_dwords - window_dword(c);  // window index of the partial dword
+        for (int e = tid; e < slotd - 1; e += 256) {
+          uint32_t lo = d0[e], hi = d0[e + 1];
+          if (tail) {
+            if (e == tl) lo = tail_dword(c);
+            if (e + 1 == tl) hi = tail_dword(c);
+          }
+#pragma unroll
+          for (int m = 1; m < EPD; m++)
+            d0[m * slotd + e] =
+                __builtin_amdgcn_alignbyte(hi, lo, m * static_cast<int>(sizeof(Tin)));
+        }
+        if (tail && tl >= 0 && tl < slotd && (tl & 255) == tid) d0[tl] = tail_dword(c);
+      }
+    };
+
+    using AccT = typename std::conditional<EPD == 4, uint32_t, float>::type;
+    AccT acc[DW][I][2];  // u8: even/odd 16-bit-lane pairs; f16: lo/hi halves
+    uint32_t tot[EPD == 4 ? DW : 1][EPD == 4 ? I : 1][4];
+#pragma unroll
+    for (int j = 0; j < DW; j++)
+#pragma unroll
+      for (int i = 0; i < I; i++) {
+        acc[j][i][0] = AccT(0);
+        acc[j][i][1] = AccT(0);
+      }
+    if constexpr (EPD == 4) {
+#pragma unroll
+      for (int j = 0; j < DW; j++)
+#pragma unroll
+        for (int i = 0; i < I; i++)
+#pragma unroll
+          for (int k = 0; k < 4; k++) tot[j][i][k] = 0;
+    }
+    auto flush = [&]() {
+      if constexpr (EPD == 4) {
+#pragma unroll
+        for (int j = 0; j < DW; j++)
+#pragma unroll
+          for (int i = 0; i < I; i++) {
+            tot[j][i][0] += acc[j][i][0] & 0xffffu;
+            tot[j][i][2] += acc[j][i][0] >> 16;
+            tot[j][i][1] += acc[j][i][1] & 0xffffu;
+            tot[j][i][3] += acc[j][i][1] >> 16;
+            acc[j][i][0] = 0;
+            acc[j][i][1] = 0;
+          }
+      }
+    };
+
+    int since_flush = 0;
+    issue(0, 0);
+    for (int s = 0; s < nstage; s++) {
+      const int buf = s & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // copy 0 of stage s landed; every wave is done with stage s-1
+      build(s, buf);
+      __syncthreads();  // shifted copies of stage s are ready
+      if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = 0; i < ncc; i++) {
+        int o[DW];
+        sload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0 + i) * TD + wave * DW, o);
+        const int chan_off = (buf * cc_max + i) * chan_dw;
+        uint32_t xs[DW][I];
+#pragma unroll
+        for (int j = 0; j < DW; j++) {
+          const uint32_t* src = lds + chan_off + o[j] + lane;
+#pragma unroll
+          for (int ii = 0; ii < I; ii++) xs[j][ii] = src[64 * ii];
+        }
+#pragma unroll
+        for (int j = 0; j < DW; j++) {
+#pragma unroll
+          for (int ii = 0; ii < I; ii++) {
+            const uint32_t x = xs[j][ii];
+            if constexpr (EPD == 4) {
+              acc[j][ii][0] += x & 0x00ff00ffu;
+              acc[j][ii][1] += (x >> 8) & 0x00ff00ffu;
+            } else {
+              float lo, hi;
+              asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]"
+                  : "=v"(lo) : "v"(x), "v"(acc[j][ii][0]));
+              asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+                  : "=v"(hi) : "v"(x), "v"(acc[j][ii][1]));
+              acc[j][ii][0] = lo;
+              acc[j][ii][1] = hi;
+            }
+          }
+        }
+        if constexpr (EPD == 4) {
+          if (++since_flush == 256) {
+            flush();
+            since_flush = 0;
+          }
+        }
+      }
+    }
+    flush();
+#pragma unroll
+    for (int j = 0; j < DW; j++) {
+      const int row = p.rows[dtile * TD + wave * DW + j];
+      if (row < 0) continue;
+#pragma unroll
+      for (int ii = 0; ii < I; ii++) {
+        const int64_t tb = t0 + static_cast<int64_t>(EPD) * (lane + 64 * ii);
+        if constexpr (EPD == 4) {
+          int32_t* o = static_cast<int32_t*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (tb + k < p.nout) o[tb + k] = static_cast<int32_t>(tot[j][ii][k]);
+        } else {
+          float* o = static_cast<float*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+          if (tb < p.nout) o[tb] = acc[j][ii][0];
+          if (tb + 1 < p.nout) o[tb + 1] = acc[j][ii][1];
+        }
+      }
+    }
+  }
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    // dwords read per copy: 64*I for the tile + shift spread + alignment, +1 for the builder
+    const int s = (64 * I + (span_max + EPD - 1 + EPD - 1) / EPD + 1 + 63) & ~63;
+    const size_t per_chan = static_cast<size_t>(s) * 4 * EPD * 2;
+    const size_t budget = 160 * 1024 / OCC;
+    if (per_chan > budget) return -1;
+    int c = cc_req;
+    while (c > 1 && per_chan * c > budget) c--;
+    *slot = s;
+    *cc = c;
+    *lds = per_chan * c;
+    return 0;
+  }
+  static constexpr int table_epd = EPD;
+};
+
+// ------------------------------------------------------------------ kernels
+
+template <class Body>
+__global__ __launch_bounds__(256, Body::OCC) void k_single(KParams p) {
   const int b = blockIdx.x;
   const int w = (b & 7) * p.per_xcd + (b >> 3);
   if (w >= p.nblocks) return;
-  const int dtile = w % p.n_dtiles;
-  const int ttile = w / p.n_dtiles;
-  const int64_t t0 = static_cast<int64_t>(ttile) * TT;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const float* in = static_cast<const float*>(p.in);
-  const int slot = p.slot;  // multiple of 64 samples
-  const int cc_max = p.cc;
-  const int nstage = (p.nchans + cc_max - 1) / cc_max;
-  const unsigned row_bytes = static_cast<unsigned>(p.nsamp) * 4u;
-  // LDS byte offset of this lane's first sample in channel slot 0 of buffer 0
-  const unsigned lane_addr =
-      static_cast<unsigned>(reinterpret_cast<uintptr_t>(lds)) + static_cast<unsigned>(lane * K * 4);
+  Body::run(p, w % p.n_dtiles, w / p.n_dtiles);
+}
 
-  // Copy the channels of stage `s` into LDS buffer `buf`; wavefront `wave`
-  // copies channels wave, wave+4, ... of the stage.
-  auto issue = [&](int s, int buf) {
-    const int c0 = s * cc_max;
-    const int ncc = min(cc_max, p.nchans - c0);
-    for (int i = wave; i < ncc; i += 4) {
-      const int c = c0 + i;
-      const int g0 = static_cast<int>(t0) + base[static_cast<int64_t>(dtile) * p.nchans + c];
-      __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<float*>(in + static_cast<int64_t>(c) * p.in_stride), 0,
-          static_cast<int>(row_bytes), 0x00020000);
-      float* dst = lds + (buf * cc_max + i) * slot;
-      for (int e = 0; e < slot; e += 64)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t*)(dst + e), 4,
-                                                 static_cast<unsigned>(g0 + e + lane) * 4u, 0, 0, 0);
+// Persistent multi-beam kernel.  Items (beam, DM tile, time tile) are
+// numbered beam by beam; the item space is cut into 8 contiguous parts, part
+// x consumed first by the workgroups on XCD x (block b runs on XCD b mod 8)
+// through counter x, and afterwards by anyone (each workgroup tries the parts
+// in turn).  Every workgroup exits once all 8 parts are exhausted.
+template <class Body>
+__global__ __launch_bounds__(256, Body::OCC) void k_batch(const KParams* __restrict__ beams,
+                                                         const int32_t* __restrict__ first_item,
+                                                         int32_t nbeams, int32_t total,
+                                                         unsigned* __restrict__ counters) {
+  __shared__ int s_item, s_beam;
+  const int xcd = blockIdx.x & 7;
+  while (true) {
+    if (threadIdx.x == 0) {
+      int item = -1;
+      for (int k = 0; k < 8 && item < 0; k++) {
+        const int x = (xcd + k) & 7;
+        const int lo = static_cast<int>((static_cast<int64_t>(total) * x) / 8);
+        const int hi = static_cast<int>((static_cast<int64_t>(total) * (x + 1)) / 8);
+        if (lo >= hi) continue;
+        const unsigned i = atomicAdd(&counters[x], 1u);
+        if (static_cast<int64_t>(lo) + i < hi) item = lo + static_cast<int>(i);
+      }
+      int beam = 0;
+      if (item >= 0)
+        while (beam + 1 < nbeams && first_item[beam + 1] <= item) beam++;
+      s_item = item;
+      s_beam = beam;
     }
-  };
-
-  float acc[DW * K];
-#pragma unroll
-  for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
-
-  issue(0, 0);
-  for (int s = 0; s < nstage; s++) {
-    const int buf = s & 1;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();  // stage s is in LDS; every wave is done with stage s-1
-    if (s + 1 < nstage) issue(s + 1, buf ^ 1);
-    const int c0 = s * cc_max;
-    const int ncc = min(cc_max, p.nchans - c0);
-    for (int i = 0; i < ncc; i++) {
-      const int c = c0 + i;
-      const int32_t* rp = rel + (static_cast<int64_t>(dtile) * p.nchans + c) * TD + wave * DW;
-      int r[DW];
-#pragma unroll
-      for (int j = 0; j < DW; j++) r[j] = rp[j];
-      STEP(acc, r, lane_addr + static_cast<unsigned>((buf * cc_max + i) * slot * 4));
-    }
-  }
-  float* out = static_cast<float*>(p.out);
-#pragma unroll
-  for (int j = 0; j < DW; j++) {
-    const int row = p.rows[dtile * TD + wave * DW + j];
-    if (row < 0) continue;
-    float* o = out + static_cast<int64_t>(row) * p.out_stride;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-      const int64_t t = t0 + lane * K + k;
-      if (t < p.nout) o[t] = acc[j * K + k];
-    }
+    __syncthreads();
+    const int item = s_item;
+    const int beam = s_beam;
+    __syncthreads();  // s_item / s_beam are rewritten on the next pass
+    if (item < 0) break;
+    const KParams p = beams[beam];
+    const int local = item - first_item[beam];
+    Body::run(p, local % p.n_dtiles, local / p.n_dtiles);
+    __syncthreads();  // LDS is reused by the next item
   }
 }
 
-constexpr size_t kLdsBudget = 64 * 1024;   // per workgroup: two groups per CU
-constexpr size_t kLdsMax = 160 * 1024;
+__global__ void k_zero(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
 
-template <typename Tin, typename Tout, int DW, int K>
-dd_status launch_lds(const TileShape& s, const TileTables& tt, const ExecArgs& a,
-                     hipStream_t stream) {
-  constexpr int TT = 64 * K;
-  const int64_t n_ttiles = (a.nout + TT - 1) / TT;
-  const int64_t nblocks64 = n_ttiles * tt.ntiles;
-  if (nblocks64 > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many tiles");
-  int slot = TT + tt.span_max;
-  slot = (slot + 15) & ~15;
-  const size_t slot_bytes = static_cast<size_t>(slot) * sizeof(Tin);
-  if (slot_bytes > kLdsMax)
-    return set_error(DD_ERR_TOO_LARGE, "shift spread inside a DM tile does not fit LDS");
-  int cc = s.chans_per_stage;
-  while (cc > 1 && slot_bytes * cc > kLdsBudget) cc--;
-  const size_t lds = slot_bytes * cc;
-  KParams p;
-  p.in = a.in;
-  p.in_stride = a.in_stride;
-  p.nsamp = a.nsamp;
-  p.out = a.out;
-  p.out_stride = a.out_stride;
-  p.nout = a.nout;
-  p.base = tt.d_base;
-  p.rel = tt.d_rel;
-  p.rows = tt.d_rows;
-  p.nchans = a.nchans;
-  p.slot = slot;
-  p.cc = cc;
-  p.n_dtiles = tt.ntiles;
-  p.nblocks = static_cast<int32_t>(nblocks64);
-  p.per_xcd = (p.nblocks + 7) / 8;
-  auto kern = k_dedisp_lds<Tin, Tout, DW, K>;
+// --------------------------------------------------------------- dispatch
+
+// One variant/type/shape combination, type-erased for the host code.
+struct Impl {
+  int (*geometry)(int span_max, int cc_req, int* slot, int* cc, size_t* lds);
+  const void* single;
+  const void* batch;
+  int td, tt, table_epd;
+  size_t in_size;
+  bool needs_dword_rows;
+};
+
+template <class Body, typename Tin>
+Impl make_impl() {
+  Impl m;
+  m.geometry = &Body::geometry;
+  m.single = reinterpret_cast<const void*>(&k_single<Body>);
+  m.batch = reinterpret_cast<const void*>(&k_batch<Body>);
+  m.td = Body::TD;
+  m.tt = Body::TT;
+  m.table_epd = Body::table_epd;
+  m.in_size = sizeof(Tin);
+  m.needs_dword_rows = Body::table_epd != 0;
+  return m;
+}
+
+bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
+  if (s.waves != 4) return false;
+  const int v = s.variant, d = s.dms_per_wave, k = s.tsamp_per_lane;
+  if (v == 0 && d == 8 && k == 8) {
+    if (in_t == DD_F32) return *out = make_impl<BodyLds<float, float, 8, 8>, float>(), true;
+    if (in_t == DD_F16) return *out = make_impl<BodyLds<_Float16, float, 8, 8>, _Float16>(), true;
+    if (in_t == DD_U8) return *out = make_impl<BodyLds<uint8_t, int32_t, 8, 8>, uint8_t>(), true;
+  }
+  if (in_t == DD_F32 && v == 1) {
+    if (d == 8 && k == 20)
+      return *out = make_impl<BodyWin<8, 20, 56, 2, dd_f32_d8_k20_w56_channel>, float>(), true;
+    if (d == 8 && k == 12)
+      return *out = make_impl<BodyWin<8, 12, 48, 3, dd_f32_d8_k12_w48_channel>, float>(), true;
+    if (d == 4 && k == 20)
+      return *out = make_impl<BodyWin<4, 20, 56, 3, dd_f32_d4_k20_w56_channel>, float>(), true;
+    if (d == 6 && k == 12)
+      return *out = make_impl<BodyWin<6, 12, 64, 3, dd_f32_d6_k12_w64_channel>, float>(), true;
+    if (d == 4 && k == 12)
+      return *out = make_impl<BodyWin<4, 12, 40, 4, dd_f32_d4_k12_w40_channel>, float>(), true;
+  }
+  if (in_t == DD_F32 && v == 2) {
+    if (d == 8 && k == 20)
+      return *out = make_impl<BodyWin<8, 20, 56, 2, dd_jt_f32_d8_k20_w56_channel>, float>(), true;
+    if (d == 8 && k == 12)
+      return *out = make_impl<BodyWin<8, 12, 48, 3, dd_jt_f32_d8_k12_w48_channel>, float>(), true;
+    if (d == 4 && k == 20)
+      return *out = make_impl<BodyWin<4, 20, 56, 3, dd_jt_f32_d4_k20_w56_channel>, float>(), true;
+  }
+  if (in_t == DD_U8 && v == 3) {
+    if (d == 8 && k == 8) return *out = make_impl<BodyCopies<uint8_t, 8, 2, 4>, uint8_t>(), true;
+    if (d == 4 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 4, 4, 4>, uint8_t>(), true;
+    if (d == 8 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 8, 4, 2>, uint8_t>(), true;
+  }
+  if (in_t == DD_F16 && v == 3) {
+    if (d == 8 && k == 8) return *out = make_impl<BodyCopies<_Float16, 8, 4, 4>, _Float16>(), true;
+    if (d == 8 && k == 4) return *out = make_impl<BodyCopies<_Float16, 8, 2, 4>, _Float16>(), true;
+  }
+  return false;
+}
+
+dd_status set_lds_limit(const void* kern, size_t lds) {
   if (lds > 64 * 1024)
-    DD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(kern, dim3(8 * p.per_xcd), dim3(256), lds, stream, p);
-  DD_HIP(hipGetLastError());
+    DD_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(lds)));
   return DD_OK;
 }
 
-
-template <int DW, int K, int WMAX, int OCC, void (*STEP)(float*, const int*, unsigned)>
-dd_status launch_win_f32(const TileShape& s, const TileTables& tt, const ExecArgs& a,
-                         hipStream_t stream) {
-  constexpr int TT = 64 * K;
-  const int64_t n_ttiles = (a.nout + TT - 1) / TT;
-  const int64_t nblocks64 = n_ttiles * tt.ntiles;
-  if (nblocks64 > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many tiles");
-  if (a.nsamp >= (int64_t(1) << 29) || a.nout + tt.span_max >= (int64_t(1) << 29))
-    return set_error(DD_ERR_TOO_LARGE, "the window kernel addresses rows with 32-bit offsets");
-  const int slot = (TT + tt.span_max + WMAX + 63) & ~63;
-  const size_t slot_bytes = static_cast<size_t>(slot) * sizeof(float);
-  constexpr size_t kBudget = 160 * 1024 / OCC;  // OCC workgroups per CU, two buffers each
-  if (2 * slot_bytes > kBudget)
-    return set_error(DD_ERR_TOO_LARGE, "shift spread inside a DM tile does not fit LDS");
-  int cc = s.chans_per_stage;
-  while (cc > 1 && 2 * slot_bytes * cc > kBudget) cc--;
-  const size_t lds = 2 * slot_bytes * cc;
+struct PreparedLaunch {
   KParams p;
+  size_t lds;
+  Impl impl;
+};
+
+// Kernel parameters of one plan/beam for shape s (tables uploaded if needed).
+dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, PreparedLaunch* out) {
+  Impl impl;
+  if (!find_impl(s, in_t, &impl))
+    return set_error(DD_ERR_NOT_IMPLEMENTED, "no kernel for this tile shape / type");
+  if (impl.needs_dword_rows &&
+      ((reinterpret_cast<uintptr_t>(a.in) & 3) || ((a.in_stride * impl.in_size) & 3)))
+    return set_error(DD_ERR_TOO_LARGE, "rows are not dword-aligned");
+  if (a.nsamp >= (int64_t(1) << 29) || a.in_stride >= (int64_t(1) << 40))
+    return set_error(DD_ERR_TOO_LARGE, "rows longer than 2^29 samples");
+  const TileTables* tt = nullptr;
+  dd_status st = plan_tiles(a.plan, impl.td, &tt);
+  if (st != DD_OK) return st;
+  int slot = 0, cc = 0;
+  size_t lds = 0;
+  if (impl.geometry(tt->span_max, s.chans_per_stage, &slot, &cc, &lds) != 0)
+    return set_error(DD_ERR_TOO_LARGE, "shift spread inside a DM tile does not fit LDS");
+  const int32_t* tab = tt->d_rel;
+  if (impl.table_epd) {
+    st = plan_aoff(a.plan, impl.td, impl.table_epd, slot, &tab);
+    if (st != DD_OK) return st;
+  }
+  const int64_t n_ttiles = (a.nout + impl.tt - 1) / impl.tt;
+  const int64_t nblocks = n_ttiles * tt->ntiles;
+  if (nblocks > INT32_MAX / 4) return set_error(DD_ERR_TOO_LARGE, "too many tiles");
+  KParams& p = out->p;
   p.in = a.in;
   p.in_stride = a.in_stride;
   p.nsamp = a.nsamp;
   p.out = a.out;
   p.out_stride = a.out_stride;
   p.nout = a.nout;
-  p.base = tt.d_base;
-  p.rel = tt.d_rel;
-  p.rows = tt.d_rows;
+  p.base = tt->d_base;
+  p.tab = tab;
+  p.rows = tt->d_rows;
   p.nchans = a.nchans;
   p.slot = slot;
   p.cc = cc;
-  p.n_dtiles = tt.ntiles;
-  p.nblocks = static_cast<int32_t>(nblocks64);
+  p.n_dtiles = tt->ntiles;
+  p.n_ttiles = static_cast<int32_t>(n_ttiles);
+  p.nblocks = static_cast<int32_t>(nblocks);
   p.per_xcd = (p.nblocks + 7) / 8;
-  auto kern = k_dedisp_win_f32<DW, K, WMAX, OCC, STEP>;
-  if (lds > 64 * 1024)
-    DD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(kern, dim3(8 * p.per_xcd), dim3(256), lds, stream, p, tt.d_rel, tt.d_base);
-  DD_HIP(hipGetLastError());
+  out->lds = lds;
+  out->impl = impl;
   return DD_OK;
 }
 
@@ -329,37 +703,71 @@ TileShape default_shape(dd_dtype in_t, const dd_plan* plan) {
   return s;
 }
 
-dd_status launch_dedisperse(const TileShape& s, const TileTables& tt, dd_dtype in_t,
-                            const ExecArgs& a, hipStream_t stream) {
-  if (s.variant == 1 && in_t == DD_F32 && s.waves == 4) {
-    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 20)
-      return launch_win_f32<8, 20, 56, 2, dd_f32_d8_k20_w56_channel>(s, tt, a, stream);
-    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 12)
-      return launch_win_f32<8, 12, 48, 3, dd_f32_d8_k12_w48_channel>(s, tt, a, stream);
-    if (s.dms_per_wave == 4 && s.tsamp_per_lane == 20)
-      return launch_win_f32<4, 20, 56, 3, dd_f32_d4_k20_w56_channel>(s, tt, a, stream);
-    if (s.dms_per_wave == 6 && s.tsamp_per_lane == 12)
-      return launch_win_f32<6, 12, 64, 3, dd_f32_d6_k12_w64_channel>(s, tt, a, stream);
-    if (s.dms_per_wave == 4 && s.tsamp_per_lane == 12)
-      return launch_win_f32<4, 12, 40, 4, dd_f32_d4_k12_w40_channel>(s, tt, a, stream);
+bool shape_supported(const TileShape& s, dd_dtype in_t) {
+  Impl m;
+  return find_impl(s, in_t, &m);
+}
+
+dd_status launch_dedisperse(const TileShape& s, dd_dtype in_t, const ExecArgs& a,
+                            hipStream_t stream) {
+  PreparedLaunch pl;
+  dd_status st = prepare(s, in_t, a, &pl);
+  if (st != DD_OK) return st;
+  st = set_lds_limit(pl.impl.single, pl.lds);
+  if (st != DD_OK) return st;
+  void* args[] = {&pl.p};
+  DD_HIP(hipLaunchKernel(pl.impl.single, dim3(8 * pl.p.per_xcd), dim3(256), args, pl.lds, stream));
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
+                        BatchLaunch* out) {
+  out->params.assign(static_cast<size_t>(n) * sizeof(KParams), 0);
+  out->first_item.assign(static_cast<size_t>(n) + 1, 0);
+  size_t lds = 0;
+  int64_t total = 0;
+  Impl impl{};
+  for (int i = 0; i < n; i++) {
+    PreparedLaunch pl;
+    dd_status st = prepare(s, in_t, beams[i], &pl);
+    if (st != DD_OK) return st;
+    impl = pl.impl;
+    std::memcpy(out->params.data() + static_cast<size_t>(i) * sizeof(KParams), &pl.p,
+                sizeof(KParams));
+    out->first_item[i] = static_cast<int32_t>(total);
+    total += pl.p.nblocks;
+    if (total > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many work items");
+    lds = std::max(lds, pl.lds);
   }
-  if (s.variant == 2 && in_t == DD_F32 && s.waves == 4) {
-    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 20)
-      return launch_win_f32<8, 20, 56, 2, dd_jt_f32_d8_k20_w56_channel>(s, tt, a, stream);
-    if (s.dms_per_wave == 8 && s.tsamp_per_lane == 12)
-      return launch_win_f32<8, 12, 48, 3, dd_jt_f32_d8_k12_w48_channel>(s, tt, a, stream);
-    if (s.dms_per_wave == 4 && s.tsamp_per_lane == 20)
-      return launch_win_f32<4, 20, 56, 3, dd_jt_f32_d4_k20_w56_channel>(s, tt, a, stream);
-  }
-  if (s.variant == 0 && s.dms_per_wave == 8 && s.waves == 4 && s.tsamp_per_lane == 8) {
-    switch (in_t) {
-      case DD_F32: return launch_lds<float, float, 8, 8>(s, tt, a, stream);
-      case DD_F16: return launch_lds<_Float16, float, 8, 8>(s, tt, a, stream);
-      case DD_U8: return launch_lds<uint8_t, int32_t, 8, 8>(s, tt, a, stream);
-      default: break;
-    }
-  }
-  return set_error(DD_ERR_NOT_IMPLEMENTED, "no kernel for this tile shape / type");
+  out->first_item[n] = static_cast<int32_t>(total);
+  out->total = static_cast<int32_t>(total);
+  out->lds = lds;
+  out->kernel = impl.batch;
+  dd_status st = set_lds_limit(impl.batch, lds);
+  if (st != DD_OK) return st;
+  int dev = 0, ncu = 0, per_cu = 0;
+  DD_HIP(hipGetDevice(&dev));
+  DD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, impl.batch, 256, lds));
+  if (per_cu < 1) return set_error(DD_ERR_TOO_LARGE, "batch kernel does not fit a CU");
+  out->grid = ((ncu * per_cu + 7) / 8) * 8;
+  return DD_OK;
+}
+
+dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
+                        unsigned* d_counters, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters, 8);
+  DD_HIP(hipGetLastError());
+  const void* params = d_params;
+  const int32_t* first = d_first;
+  int32_t nbeams = static_cast<int32_t>(b.first_item.size()) - 1;
+  int32_t total = b.total;
+  unsigned* counters = d_counters;
+  void* args[] = {&params, &first, &nbeams, &total, &counters};
+  DD_HIP(hipLaunchKernel(b.kernel, dim3(b.grid), dim3(256), args, b.lds, stream));
+  return DD_OK;
 }
 
 }  // namespace dd

@@ -111,7 +111,8 @@ dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out) {
   const int nch = plan->nchans;
   const int ntiles = (plan->ndms + td - 1) / td;
   std::vector<int32_t> base(static_cast<size_t>(ntiles) * nch);
-  std::vector<int32_t> rel(static_cast<size_t>(ntiles) * nch * td);
+  // +8: kernels fetch a wavefront's entries with one 4- or 8-dword scalar load
+  std::vector<int32_t> rel(static_cast<size_t>(ntiles) * nch * td + 8, 0);
   std::vector<int32_t> rows(static_cast<size_t>(ntiles) * td, -1);
   TileTables tt;
   tt.td = td;
@@ -157,6 +158,52 @@ dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out) {
   return DD_OK;
 }
 
+dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** out) {
+  const TileTables* tt = nullptr;
+  dd_status st = plan_tiles(plan, td, &tt);
+  if (st != DD_OK) return st;
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceTables& dt = plan->dev[dev];
+  const auto key = std::make_tuple(td, epd, slotd);
+  auto it = dt.aoff.find(key);
+  if (it != dt.aoff.end()) {
+    *out = it->second;
+    return DD_OK;
+  }
+  const int nch = plan->nchans;
+  const int ntiles = tt->ntiles;
+  const int sh = epd == 4 ? 2 : (epd == 2 ? 1 : 0);
+  std::vector<int32_t> host(static_cast<size_t>(ntiles) * nch * td + 8, 0);
+  for (int tile = 0; tile < ntiles; tile++) {
+    const int first = tile * td;
+    const int count = std::min(td, plan->ndms - first);
+    for (int c = 0; c < nch; c++) {
+      int32_t lo = INT32_MAX;
+      for (int j = 0; j < count; j++)
+        lo = std::min(lo, plan->delays[static_cast<size_t>(plan->order[first + j]) * nch + c]);
+      const int a = lo & (epd - 1);
+      for (int j = 0; j < td; j++) {
+        const int src = plan->order[first + (j < count ? j : 0)];
+        const int R = a + plan->delays[static_cast<size_t>(src) * nch + c] - lo;
+        host[(static_cast<size_t>(tile) * nch + c) * td + j] = (R & (epd - 1)) * slotd + (R >> sh);
+      }
+    }
+  }
+  int32_t* d = nullptr;
+  hipError_t e = hipMalloc(&d, host.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(d, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_error(e, "uploading copy offsets");
+  }
+  dt.aoff.emplace(key, d);
+  *out = d;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 dd_plan::~dd_plan() {
@@ -169,6 +216,7 @@ dd_plan::~dd_plan() {
       (void)hipFree(t.second.d_rel);
       (void)hipFree(t.second.d_rows);
     }
+    for (auto& t : kv.second.aoff) (void)hipFree(t.second);
     (void)hipSetDevice(cur);
   }
 }

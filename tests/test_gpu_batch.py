@@ -1,0 +1,134 @@
+"""Batched many-beam execution: one persistent, graph-captured launch over
+beams of different channel counts, DM lists and lengths.
+
+Every beam of a batch must equal (bit for bit, same tile shape, same
+arithmetic order) the single-plan dd_execute of that beam, and the oracle
+(bit-exact for 8-bit input, FP tolerance for float input).  The captured graph
+is replayed several times with the program's own eager GPU work and
+synchronisations in between, and every replay is checked.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1107_2516_amd as dd
+import synth
+from helpers import FP_TOL, make_input, rand_table, scaled_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _beams(dtype, seed):
+    g = np.random.default_rng(seed)
+    shapes = [(64, 40, 3000, 300), (200, 70, 2500, 500), (7, 5, 900, 60), (130, 33, 4100, 800),
+              (300, 90, 1777, 200)]
+    out = []
+    for nchans, ndms, nsamp, maxd in shapes:
+        tab = np.sort(rand_table(g, ndms, nchans, maxd), axis=0)
+        x = make_input(g, dtype, nchans, nsamp)
+        out.append((tab, x))
+    return out
+
+
+def _check(y, x, tab, dtype):
+    if dtype == "u8":
+        assert np.array_equal(y.astype(np.int64), oracle.dedisperse(x, tab))
+    else:
+        e, _ = scaled_error(y, x, tab)
+        assert e <= FP_TOL, e
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32", "f16"])
+def test_batch_equals_single_and_oracle(dtype):
+    beams = _beams(dtype, 10 + len(dtype))
+    plans = [dd.Plan.from_delays(t) for t, _ in beams]
+    xs = [torch.from_numpy(x).cuda() for _, x in beams]
+    b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    info = b.info()
+    assert info["work_items"] > 0 and info["grid"] >= 8
+    outs = b.launch()
+    torch.cuda.synchronize()
+    for (tab, x), p, xt, o in zip(beams, plans, xs, outs):
+        single = p.execute_tiled(xt, info["tile"])
+        torch.cuda.synchronize()
+        assert torch.equal(o, single)
+        _check(o.cpu().numpy(), x, tab, dtype)
+
+
+def test_batch_graph_replays_and_update():
+    beams = _beams("u8", 3)
+    plans = [dd.Plan.from_delays(t) for t, _ in beams]
+    xs = [torch.from_numpy(x).cuda() for _, x in beams]
+    b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    refs = [oracle.dedisperse(x, t) for t, x in beams]
+    for rep in range(4):
+        for o in b.outputs:
+            o.fill_(-7)  # eager work between replays
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        for o, r in zip(b.outputs, refs):
+            assert np.array_equal(o.cpu().numpy().astype(np.int64), r), rep
+    # new inputs and outputs of the same shapes: no re-capture needed
+    g = np.random.default_rng(99)
+    new_x = [make_input(g, "u8", x.shape[0], x.shape[1]) for _, x in beams]
+    new_in = [torch.from_numpy(x).cuda() for x in new_x]
+    new_out = [torch.full_like(o, -1) for o in b.outputs]
+    b.update(inputs=new_in, outputs=new_out)
+    for rep in range(2):
+        b.launch()
+        torch.cuda.synchronize()
+        for o, (t, _), x in zip(new_out, beams, new_x):
+            assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t)), rep
+
+
+def test_batch_update_rejects_shape_change():
+    beams = _beams("u8", 4)
+    plans = [dd.Plan.from_delays(t) for t, _ in beams]
+    xs = [torch.from_numpy(x).cuda() for _, x in beams]
+    b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    bad = list(xs)
+    bad[0] = torch.zeros((xs[0].shape[0], xs[0].shape[1] + 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(dd.DedispError) as ei:
+        b.update(inputs=bad)
+    assert ei.value.status == dd.DD_ERR_INVALID_ARG
+
+
+def test_batch_autotune_keeps_results():
+    beams = _beams("u8", 5)
+    plans = [dd.Plan.from_delays(t) for t, _ in beams]
+    xs = [torch.from_numpy(x).cuda() for _, x in beams]
+    b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    cfg, ms = b.autotune()
+    assert ms > 0 and b.info()["tile"] == cfg
+    b.launch()
+    torch.cuda.synchronize()
+    for o, (t, x) in zip(b.outputs, beams):
+        assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t))
+
+
+def test_batch_workload_subset_sampled_rows():
+    """Six beams of the many-beam workload (1214-1510 MHz, 64 us, nchans in
+    {256, 512, 1024}, up to 4096 DMs), 8-bit noise; sampled DM rows checked
+    in full against the oracle."""
+    specs = synth.batch_beams()[:6]
+    plans, xs, items = [], [], []
+    for sp in specs:
+        bd = sp["band"]
+        dms = synth.dm_grid(sp["ndms"], sp["step"])
+        p = dd.Plan(bd.nchans, bd.f_top, bd.df, bd.t_samp, dms)
+        x = synth.quantize_u8(synth.noise(bd.nchans, sp["nsamp"], sp["seed"]))
+        plans.append(p)
+        xs.append(x)
+        items.append((p, torch.from_numpy(x).cuda(), None))
+    b = dd.Batch(items)
+    b.launch()
+    torch.cuda.synchronize()
+    for sp, p, x, o in zip(specs, plans, xs, b.outputs):
+        bd = sp["band"]
+        tab = oracle.delay_table(bd.nchans, bd.f_top, bd.df, bd.t_samp,
+                                 synth.dm_grid(sp["ndms"], sp["step"]))
+        rows = [0, p.ndms // 3, p.ndms - 1]
+        ref = oracle.dedisperse(x, tab, rows=rows)
+        assert np.array_equal(o[rows].cpu().numpy().astype(np.int64), ref)

@@ -200,3 +200,63 @@ def test_f32_kernel_variants(tile, maxd):
     torch.cuda.synchronize()
     e, _ = scaled_error(y.cpu().numpy(), x, tab)
     assert e <= FP_TOL, e
+
+
+TILES_COPIES = [
+    ("u8", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)),
+    ("u8", dict(variant=3, dms_per_wave=4, waves=4, tsamp_per_lane=16, chans_per_stage=8)),
+    ("u8", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=4)),
+    ("f16", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)),
+    ("f16", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=4, chans_per_stage=8)),
+]
+
+
+@pytest.mark.parametrize("dtype,tile", TILES_COPIES,
+                         ids=[f"{d}_d{t['dms_per_wave']}_k{t['tsamp_per_lane']}" for d, t in TILES_COPIES])
+@pytest.mark.parametrize("nsamp", [3001, 3002, 3003, 3004, 700])
+def test_copies_kernel(dtype, tile, nsamp):
+    """The aligned-copies kernel for 8-bit and half input: every shift residue
+    modulo the samples per dword, rows whose length is not a whole number of
+    dwords (the partial last dword is patched from global memory), more than
+    256 channels (the 16-bit lane flush), ragged DM and time tiles."""
+    g = np.random.default_rng(nsamp + len(dtype))
+    nchans, ndms = 300, 70
+    tab = np.sort(rand_table(g, ndms, nchans, 280 if nsamp > 1000 else 150), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, dtype, nchans, nsamp)
+    if dtype == "u8":
+        x[:, -3:] = 255  # the last samples matter for the final outputs
+    # dword-aligned row stride, ragged row length
+    stride = (nsamp + 3) // 4 * 4
+    big = np.full((nchans, stride), 77 if dtype == "u8" else 9.0, dtype=x.dtype)
+    big[:, :nsamp] = x
+    y = plan.execute_tiled(torch.from_numpy(big).cuda()[:, :nsamp], tile)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    if dtype == "u8":
+        assert np.array_equal(y.astype(np.int64), oracle.dedisperse(x, tab))
+    else:
+        e, _ = scaled_error(y, x, tab)
+        assert e <= FP_TOL, e
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16"])
+def test_unaligned_rows_fall_back(dtype):
+    """Rows that do not start on a dword boundary take the LDS-streaming
+    kernel; results are unchanged."""
+    g = np.random.default_rng(77)
+    nchans, ndms, nsamp = 40, 33, 2001
+    tab = rand_table(g, ndms, nchans, 200)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, dtype, nchans, nsamp)
+    big = np.zeros((nchans, nsamp + 1), dtype=x.dtype)
+    big[:, :nsamp] = x
+    xt = torch.from_numpy(big).cuda()[:, :nsamp]  # row stride nsamp + 1: not dword-aligned
+    y = plan.execute(xt)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    if dtype == "u8":
+        assert np.array_equal(y.astype(np.int64), oracle.dedisperse(x, tab))
+    else:
+        e, _ = scaled_error(y, x, tab)
+        assert e <= FP_TOL
