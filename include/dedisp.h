@@ -210,7 +210,8 @@ typedef struct dd_serve_config {
   dd_dtype out_t;          /* output type (pair rules as dd_execute) */
   int32_t max_inflight;    /* chunks on the device at once (>= 1) */
   int32_t queue_capacity;  /* host submit queue length (>= 1) */
-  int32_t nstreams;        /* HIP streams used to overlap chunks (>= 1) */
+  int32_t nstreams;        /* HIP streams used to overlap chunks (1..16) */
+  size_t host_staging_bytes; /* pinned host pool for queued chunks (0 = 1 GiB) */
 } dd_serve_config;
 
 typedef struct dd_result {
@@ -244,11 +245,13 @@ dd_status dd_serve_add_beam(dd_server* srv, const dd_plan* plan, int64_t max_chu
 
 /*
  * Queue one chunk: nsamp samples of every channel, host memory laid out
- * [nchans][nsamp] (pinned memory is copied asynchronously).  The chunk is
- * copied before this call returns.  seq must increase by one per beam;
- * a gap restarts the beam (its carry is dropped and it warms up again).
- * DD_ERR_AGAIN when the queue is full, DD_ERR_TOO_LARGE when nsamp exceeds
- * the beam's max_chunk.
+ * [nchans][nsamp].  The chunk is copied into the server's pinned staging pool
+ * before this call returns.  seq must increase by one per beam; a gap
+ * restarts the beam (its carry is dropped and it warms up again).  Chunks of
+ * one beam must be submitted from one thread at a time.
+ * DD_ERR_AGAIN when the queue or the staging pool is full (poll, release and
+ * retry), DD_ERR_TOO_LARGE when nsamp exceeds the beam's max_chunk,
+ * DD_ERR_NOT_FOUND for an unknown beam.
  */
 dd_status dd_serve_submit(dd_server* srv, int32_t beam, const void* h_chunk, int64_t nsamp,
                           int64_t seq, uint64_t* ticket);
@@ -259,8 +262,15 @@ dd_status dd_serve_poll(dd_server* srv, dd_result* out, int32_t max, int32_t* n)
 /* Return a finished chunk's output memory to the arena. */
 dd_status dd_serve_release(dd_server* srv, uint64_t ticket);
 
-/* Wait until every queued chunk has finished (results stay pollable). */
+/* Wait until every queued chunk has finished (results stay pollable).  A
+ * chunk waiting for arena memory finishes only after results are released,
+ * so release what you poll before draining. */
 dd_status dd_serve_drain(dd_server* srv);
+
+/* Queue state: chunks waiting for admission, on the device, finished but not
+ * released; and the largest free block of the arena.  Any pointer may be NULL. */
+dd_status dd_serve_stats(dd_server* srv, int32_t* pending, int32_t* inflight, int32_t* finished,
+                         size_t* largest_free);
 
 dd_status dd_serve_destroy(dd_server* srv);
 

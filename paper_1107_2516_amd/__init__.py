@@ -62,7 +62,8 @@ class BatchItem(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("in_t", ctypes.c_int), ("out_t", ctypes.c_int), ("max_inflight", ctypes.c_int32),
-                ("queue_capacity", ctypes.c_int32), ("nstreams", ctypes.c_int32)]
+                ("queue_capacity", ctypes.c_int32), ("nstreams", ctypes.c_int32),
+                ("host_staging_bytes", ctypes.c_size_t)]
 
 
 class Result(ctypes.Structure):
@@ -105,6 +106,8 @@ _SIGS = {
     "dd_serve_release": [_P, ctypes.c_uint64],
     "dd_serve_drain": [_P],
     "dd_serve_destroy": [_P],
+    "dd_serve_stats": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                       ctypes.POINTER(ctypes.c_size_t)],
 }
 
 
@@ -347,6 +350,88 @@ class Batch:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.dd_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Streaming server: chunks of many beams, continuous batching on the GPU.
+
+    arena: a uint8 CUDA tensor whose memory the server sub-allocates (beam
+    carries, chunk outputs); it must outlive the server.
+    """
+
+    def __init__(self, arena, in_dtype, max_inflight=8, queue_capacity=256, nstreams=4,
+                 host_staging_bytes=0):
+        self.arena = arena
+        self.in_dtype = in_dtype
+        self.out_dtype = out_dtype_for(in_dtype)
+        cfg = ServeConfig(dtype_code(in_dtype), dtype_code(self.out_dtype), max_inflight,
+                          queue_capacity, nstreams, host_staging_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().dd_serve_create(ctypes.byref(cfg), arena.data_ptr(),
+                                     arena.numel() * arena.element_size(), ctypes.byref(h)))
+        self._h = h
+        self.beams = []
+
+    def add_beam(self, plan, max_chunk):
+        b = _I32()
+        _check(lib().dd_serve_add_beam(self._h, plan.handle, int(max_chunk), ctypes.byref(b)))
+        self.beams.append(plan)
+        return b.value
+
+    def submit(self, beam, chunk: np.ndarray, seq):
+        """Queue a host chunk [nchans, nsamp] (C-contiguous numpy array).
+        Returns the ticket, or None when the server is full (DD_ERR_AGAIN)."""
+        c = np.ascontiguousarray(chunk)
+        t = ctypes.c_uint64()
+        st = lib().dd_serve_submit(self._h, int(beam), c.ctypes.data, int(c.shape[1]), int(seq),
+                                   ctypes.byref(t))
+        if st == DD_ERR_AGAIN:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, max_results=64):
+        arr = (Result * max_results)()
+        n = _I32()
+        _check(lib().dd_serve_poll(self._h, arr, max_results, ctypes.byref(n)))
+        return [arr[i] for i in range(n.value)]
+
+    def output(self, result):
+        """The device output of a finished chunk as a tensor view into the
+        arena, [ndms, nout] (valid until release)."""
+        plan = self.beams[result.beam]
+        if result.nout == 0:
+            return None
+        torch = _torch()
+        esize = 4
+        off = result.d_out - self.arena.data_ptr()
+        flat = self.arena[off: off + plan.ndms * result.out_stride * esize].view(self.out_dtype)
+        return flat.view(plan.ndms, result.out_stride)[:, : result.nout]
+
+    def release(self, ticket):
+        _check(lib().dd_serve_release(self._h, int(ticket)))
+
+    def stats(self):
+        p, i, f, z = _I32(), _I32(), _I32(), ctypes.c_size_t()
+        _check(lib().dd_serve_stats(self._h, ctypes.byref(p), ctypes.byref(i), ctypes.byref(f),
+                                    ctypes.byref(z)))
+        return {"pending": p.value, "inflight": i.value, "finished": f.value,
+                "largest_free": z.value}
+
+    def drain(self):
+        _check(lib().dd_serve_drain(self._h))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_serve_destroy(h)
         self._h = None
 
     def __del__(self):

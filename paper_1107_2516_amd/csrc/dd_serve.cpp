@@ -1,24 +1,495 @@
-// Streaming server with continuous batching.
+// Streaming server: continuous batching of filterbank chunks from many beams.
+//
+// Each beam owns a device buffer of (max_shift + max_chunk) samples per
+// channel holding its overlap carry (the last max_shift samples it has
+// received, section 3 "Maximum shift") followed by the newest chunk.  A chunk
+// of n samples that brings the beam's total to S emits the outputs for
+// absolute times [E_prev, E_new) with E = max(0, S - max_shift); while fewer
+// than max_shift + 1 samples have arrived the beam is warming up and emits
+// nothing.  After the de-dispersion the new carry is moved to the front of
+// the buffer through a per-stream temporary.
+//
+// All device memory (beam buffers, chunk outputs, temporaries) is
+// sub-allocated from the caller's arena; a chunk is admitted only when its
+// output fits (the memory rule of section 3, "Processable Samples").  Chunks
+// are staged in a pinned host pool at submit time.  A scheduler thread admits
+// chunks in arrival order (a beam's chunks strictly in order, other beams may
+// overtake a chunk that is waiting for memory), enqueues
+//   host->device copy, de-dispersion, carry move, completion event
+// on the beam's stream (beams are spread over the server's streams, so work
+// of different beams overlaps on the device while others are admitted), and
+// retires chunks as their events complete.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <thread>
+#include <unordered_map>
+
 #include "dd_internal.h"
 
+namespace dd {
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over a byte range (offsets), 256-byte granules.
+class RangeAlloc {
+ public:
+  explicit RangeAlloc(size_t size = 0) { reset(size); }
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_.emplace_back(0, size);
+    size_ = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        it->first += bytes;
+        it->second -= bytes;
+        if (it->second == 0) free_.erase(it);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = free_.begin();
+    while (it != free_.end() && it->first < off) ++it;
+    it = free_.emplace(it, off, bytes);
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (auto& f : free_) m = std::max(m, f.second);
+    return m;
+  }
+
+ private:
+  std::list<std::pair<size_t, size_t>> free_;
+  size_t size_ = 0;
+};
+
+struct Chunk {
+  uint64_t ticket = 0;
+  int32_t beam = 0;
+  int64_t seq = 0, nsamp = 0;
+  size_t h_off = 0, h_bytes = 0;  // pinned staging
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int32_t status = DD_OK;
+  int64_t t_first = 0, nout = 0, out_stride = 0;
+  size_t out_off = 0, out_bytes = 0;
+  void* d_out = nullptr;
+  hipEvent_t ev = nullptr;
+  bool restart = false;
+};
+
+struct Beam {
+  const dd_plan* plan = nullptr;
+  int64_t max_chunk = 0, cap = 0;  // cap: samples per channel row of the buffer
+  size_t buf_off = 0, buf_bytes = 0;
+  unsigned char* d_buf = nullptr;
+  int64_t S = 0, E = 0;     // samples enqueued, outputs emitted (absolute)
+  int64_t next_seq = 0;     // expected seq of the next submitted chunk
+  int stream = 0;
+  int pending = 0;          // submitted, not yet admitted
+};
+
+}  // namespace
+}  // namespace dd
+
+struct dd_server {
+  dd_serve_config cfg{};
+  size_t esize = 1, osize = 4;
+  unsigned char* arena = nullptr;
+  dd::RangeAlloc dev_alloc;
+  unsigned char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  dd::RangeAlloc host_alloc;
+  std::vector<dd::Beam> beams;
+  std::vector<hipStream_t> streams;
+  std::vector<unsigned char*> temps;  // per stream, carry-move temporary
+  std::vector<size_t> temp_size;
+  std::deque<dd::Chunk*> pending;
+  std::vector<dd::Chunk*> inflight;
+  std::unordered_map<uint64_t, dd::Chunk*> done;  // finished, not yet polled or released
+  std::deque<uint64_t> ready;                     // finished, not yet polled
+  uint64_t next_ticket = 1;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  std::thread worker;
+  ~dd_server();
+  void run();
+  bool admit_locked(dd::Chunk* c);
+  void retire_locked();
+};
+
+namespace dd {
+namespace {
+
+dd_status enqueue_chunk(dd_server* s, Beam& b, Chunk* c, hipStream_t st) {
+  const dd_plan* plan = b.plan;
+  const int64_t nch = plan->nchans;
+  const int64_t carry = b.S - b.E;  // samples at the front of the buffer
+  // host -> device: the chunk goes right after the carry
+  DD_HIP(hipMemcpy2DAsync(b.d_buf + carry * s->esize, static_cast<size_t>(b.cap) * s->esize,
+                          s->pinned + c->h_off, static_cast<size_t>(c->nsamp) * s->esize,
+                          static_cast<size_t>(c->nsamp) * s->esize, static_cast<size_t>(nch),
+                          hipMemcpyHostToDevice, st));
+  const int64_t S2 = b.S + c->nsamp;
+  const int64_t E2 = std::max<int64_t>(0, S2 - plan->max_shift);
+  c->t_first = b.E;
+  c->nout = E2 - b.E;
+  if (c->nout > 0) {
+    const int64_t len = S2 - b.E;  // buffer samples holding absolute times [E, S2)
+    dd_status st2 = dd_execute(plan, b.d_buf, s->cfg.in_t, len, b.cap, c->d_out, s->cfg.out_t,
+                               c->out_stride, st);
+    if (st2 != DD_OK) return st2;
+    // the new carry, absolute [E2, S2), moves to the front of the buffer
+    const int64_t keep = S2 - E2;
+    const int64_t from = E2 - b.E;
+    if (keep > 0 && from > 0) {
+      unsigned char* tmp = s->temps[b.stream];
+      const size_t row = static_cast<size_t>(keep) * s->esize;
+      DD_HIP(hipMemcpy2DAsync(tmp, row, b.d_buf + from * s->esize,
+                              static_cast<size_t>(b.cap) * s->esize, row, static_cast<size_t>(nch),
+                              hipMemcpyDeviceToDevice, st));
+      DD_HIP(hipMemcpy2DAsync(b.d_buf, static_cast<size_t>(b.cap) * s->esize, tmp, row, row,
+                              static_cast<size_t>(nch), hipMemcpyDeviceToDevice, st));
+    }
+  }
+  b.S = S2;
+  b.E = E2;
+  DD_HIP(hipEventRecord(c->ev, st));
+  return DD_OK;
+}
+
+}  // namespace
+}  // namespace dd
+
+bool dd_server::admit_locked(dd::Chunk* c) {
+  dd::Beam& b = beams[c->beam];
+  if (c->restart) {
+    b.S = 0;
+    b.E = 0;
+  }
+  const int64_t S2 = b.S + c->nsamp;
+  const int64_t E2 = std::max<int64_t>(0, S2 - b.plan->max_shift);
+  const int64_t nout = E2 - b.E;
+  if (nout > 0) {
+    c->out_stride = (nout + 63) & ~int64_t(63);
+    c->out_bytes = static_cast<size_t>(b.plan->ndms) * c->out_stride * osize;
+    if (!dev_alloc.alloc(c->out_bytes, &c->out_off)) return false;  // wait for releases
+    c->d_out = arena + c->out_off;
+  }
+  c->t_admit = dd::now_s();
+  dd_status st = dd::enqueue_chunk(this, b, c, streams[b.stream]);
+  if (st != DD_OK) {
+    c->status = st;
+    // the beam's buffer state is unknown after a failed enqueue: restart it
+    b.S = 0;
+    b.E = 0;
+  }
+  return true;
+}
+
+void dd_server::retire_locked() {
+  for (size_t i = 0; i < inflight.size();) {
+    dd::Chunk* c = inflight[i];
+    hipError_t q = hipEventQuery(c->ev);
+    if (q == hipErrorNotReady) {
+      i++;
+      continue;
+    }
+    if (q != hipSuccess && c->status == DD_OK) c->status = DD_ERR_HIP;
+    c->t_done = dd::now_s();
+    host_alloc.release(c->h_off, c->h_bytes);
+    c->h_bytes = 0;
+    done[c->ticket] = c;
+    ready.push_back(c->ticket);
+    inflight[i] = inflight.back();
+    inflight.pop_back();
+    cv_done.notify_all();
+  }
+}
+
+void dd_server::run() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  while (!stop) {
+    // admission: arrival order, a beam's chunks in order, others may overtake
+    std::vector<int> blocked(beams.size(), 0);
+    for (auto it = pending.begin(); it != pending.end();) {
+      dd::Chunk* c = *it;
+      if (static_cast<int>(inflight.size()) >= cfg.max_inflight) break;
+      if (blocked[c->beam]) {
+        ++it;
+        continue;
+      }
+      if (!admit_locked(c)) {
+        blocked[c->beam] = 1;
+        ++it;
+        continue;
+      }
+      beams[c->beam].pending--;
+      if (c->status != DD_OK) {
+        // failed to enqueue: report now
+        c->t_done = dd::now_s();
+        host_alloc.release(c->h_off, c->h_bytes);
+        c->h_bytes = 0;
+        if (c->d_out) {
+          dev_alloc.release(c->out_off, c->out_bytes);
+          c->d_out = nullptr;
+        }
+        done[c->ticket] = c;
+        ready.push_back(c->ticket);
+        cv_done.notify_all();
+      } else {
+        inflight.push_back(c);
+      }
+      it = pending.erase(it);
+    }
+    retire_locked();
+    if (inflight.empty() && pending.empty()) {
+      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+    } else if (inflight.empty()) {
+      // everything pending waits for arena memory: sleep until a release
+      cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    } else {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    }
+  }
+}
+
+dd_server::~dd_server() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;
+  }
+  cv_work.notify_all();
+  if (worker.joinable()) worker.join();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+  auto drop = [](dd::Chunk* c) {
+    if (c->ev) (void)hipEventDestroy(c->ev);
+    delete c;
+  };
+  for (dd::Chunk* c : pending) drop(c);
+  for (dd::Chunk* c : inflight) drop(c);
+  for (auto& kv : done) drop(kv.second);
+  for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+  if (pinned) (void)hipHostFree(pinned);
+  (void)hipSetDevice(cur);
+}
+
 extern "C" {
-dd_status dd_serve_create(const dd_serve_config*, void*, size_t, dd_server**) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "serving not built yet");
+
+dd_status dd_serve_create(const dd_serve_config* cfg, void* d_arena, size_t arena_bytes,
+                          dd_server** out) {
+  try {
+    if (!cfg || !out || !d_arena || arena_bytes == 0)
+      return dd::set_error(DD_ERR_INVALID_ARG, "NULL config, arena or out");
+    if (!dd::dtype_pair_ok(cfg->in_t, cfg->out_t))
+      return dd::set_error(DD_ERR_DTYPE, "supported pairs: f32->f32, f16->f32, u8->i32");
+    if (cfg->max_inflight < 1 || cfg->queue_capacity < 1 || cfg->nstreams < 1 || cfg->nstreams > 16)
+      return dd::set_error(DD_ERR_INVALID_ARG, "max_inflight, queue_capacity >= 1, 1 <= nstreams <= 16");
+    std::unique_ptr<dd_server> s(new dd_server());
+    s->cfg = *cfg;
+    s->esize = dd::dtype_size(cfg->in_t);
+    s->osize = dd::dtype_size(cfg->out_t);
+    s->arena = static_cast<unsigned char*>(d_arena);
+    s->dev_alloc.reset(arena_bytes);
+    s->pinned_bytes = cfg->host_staging_bytes ? cfg->host_staging_bytes : (size_t(1) << 30);
+    DD_HIP(hipGetDevice(&s->device));
+    DD_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->pinned), s->pinned_bytes, hipHostMallocDefault));
+    s->host_alloc.reset(s->pinned_bytes);
+    for (int i = 0; i < cfg->nstreams; i++) {
+      hipStream_t st = nullptr;
+      DD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      s->streams.push_back(st);
+      s->temps.push_back(nullptr);
+      s->temp_size.push_back(0);
+    }
+    dd_server* raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+    *out = s.release();
+    return DD_OK;
+  } catch (const std::bad_alloc&) {
+    return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
 }
-dd_status dd_serve_add_beam(dd_server*, const dd_plan*, int64_t, int32_t*) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "serving not built yet");
+
+dd_status dd_serve_add_beam(dd_server* s, const dd_plan* plan, int64_t max_chunk, int32_t* beam) {
+  try {
+    if (!s || !plan || !beam || max_chunk < 1)
+      return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument or max_chunk < 1");
+    std::lock_guard<std::mutex> lk(s->mu);
+    dd::Beam b;
+    b.plan = plan;
+    b.max_chunk = max_chunk;
+    b.cap = (plan->max_shift + max_chunk + 63) & ~int64_t(63);
+    b.buf_bytes = static_cast<size_t>(b.cap) * plan->nchans * s->esize;
+    if (!s->dev_alloc.alloc(b.buf_bytes, &b.buf_off))
+      return dd::set_error(DD_ERR_TOO_LARGE, "the beam's carry buffer does not fit the arena");
+    b.d_buf = s->arena + b.buf_off;
+    b.stream = static_cast<int>(s->beams.size()) % s->cfg.nstreams;
+    // the carry-move temporary of the beam's stream must hold this beam's carry
+    const size_t need = std::max<size_t>(
+        static_cast<size_t>(plan->max_shift) * plan->nchans * s->esize, 256);
+    if (need > s->temp_size[b.stream]) {
+      size_t off = 0;
+      if (!s->dev_alloc.alloc(need, &off)) {
+        s->dev_alloc.release(b.buf_off, b.buf_bytes);
+        return dd::set_error(DD_ERR_TOO_LARGE, "the carry temporary does not fit the arena");
+      }
+      // a smaller temporary of this stream may still be used by queued work:
+      // it stays allocated until the server is destroyed
+      s->temps[b.stream] = s->arena + off;
+      s->temp_size[b.stream] = need;
+    }
+    *beam = static_cast<int32_t>(s->beams.size());
+    s->beams.push_back(b);
+    return DD_OK;
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
 }
-dd_status dd_serve_submit(dd_server*, int32_t, const void*, int64_t, int64_t, uint64_t*) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "serving not built yet");
+
+dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64_t nsamp,
+                          int64_t seq, uint64_t* ticket) {
+  try {
+    if (!s || !h_chunk || !ticket) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+    const double t = dd::now_s();
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (beam < 0 || beam >= static_cast<int32_t>(s->beams.size()))
+      return dd::set_error(DD_ERR_NOT_FOUND, "unknown beam");
+    dd::Beam& b = s->beams[beam];
+    if (nsamp < 1 || nsamp > b.max_chunk)
+      return dd::set_error(DD_ERR_TOO_LARGE, "chunk longer than the beam's max_chunk");
+    if (static_cast<int32_t>(s->pending.size()) >= s->cfg.queue_capacity)
+      return dd::set_error(DD_ERR_AGAIN, "submit queue full");
+    const size_t bytes = static_cast<size_t>(nsamp) * b.plan->nchans * s->esize;
+    size_t off = 0;
+    if (!s->host_alloc.alloc(bytes, &off)) return dd::set_error(DD_ERR_AGAIN, "staging pool full");
+    std::unique_ptr<dd::Chunk> c(new dd::Chunk());
+    hipError_t e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      s->host_alloc.release(off, bytes);
+      return dd::hip_error(e, "hipEventCreate");
+    }
+    c->ticket = s->next_ticket++;
+    c->beam = beam;
+    c->seq = seq;
+    c->nsamp = nsamp;
+    c->h_off = off;
+    c->h_bytes = bytes;
+    c->t_submit = t;
+    c->restart = seq != b.next_seq;  // a gap (or the first chunk after one) restarts the beam
+    b.next_seq = seq + 1;
+    b.pending++;
+    lk.unlock();
+    std::memcpy(s->pinned + off, h_chunk, bytes);  // outside the lock; the chunk is not queued yet
+    lk.lock();
+    *ticket = c->ticket;
+    s->pending.push_back(c.release());
+    s->cv_work.notify_all();
+    return DD_OK;
+  } catch (const std::bad_alloc&) {
+    return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
 }
-dd_status dd_serve_poll(dd_server*, dd_result*, int32_t, int32_t*) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "serving not built yet");
+
+dd_status dd_serve_poll(dd_server* s, dd_result* out, int32_t max, int32_t* n) {
+  if (!s || !n || (max > 0 && !out)) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int32_t k = 0;
+  while (k < max && !s->ready.empty()) {
+    const uint64_t t = s->ready.front();
+    s->ready.pop_front();
+    auto it = s->done.find(t);
+    if (it == s->done.end()) continue;
+    const dd::Chunk* c = it->second;
+    dd_result& r = out[k++];
+    r.ticket = c->ticket;
+    r.beam = c->beam;
+    r.status = c->status;
+    r.seq = c->seq;
+    r.t_first = c->t_first;
+    r.nout = c->status == DD_OK ? c->nout : 0;
+    r.d_out = c->d_out;
+    r.out_stride = c->out_stride;
+    r.t_submit = c->t_submit;
+    r.t_admit = c->t_admit;
+    r.t_done = c->t_done;
+  }
+  *n = k;
+  return DD_OK;
 }
-dd_status dd_serve_release(dd_server*, uint64_t) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "serving not built yet");
+
+dd_status dd_serve_release(dd_server* s, uint64_t ticket) {
+  if (!s) return dd::set_error(DD_ERR_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->done.find(ticket);
+  if (it == s->done.end()) return dd::set_error(DD_ERR_NOT_FOUND, "unknown or unfinished ticket");
+  dd::Chunk* c = it->second;
+  if (c->d_out) s->dev_alloc.release(c->out_off, c->out_bytes);
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  delete c;
+  s->done.erase(it);
+  s->cv_work.notify_all();  // memory freed: admission may proceed
+  return DD_OK;
 }
-dd_status dd_serve_drain(dd_server*) {
-  return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "serving not built yet");
+
+dd_status dd_serve_drain(dd_server* s) {
+  if (!s) return dd::set_error(DD_ERR_INVALID_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->inflight.empty(); });
+  return DD_OK;
 }
-dd_status dd_serve_destroy(dd_server*) { return DD_OK; }
+
+dd_status dd_serve_stats(dd_server* s, int32_t* pending, int32_t* inflight, int32_t* finished,
+                         size_t* free_bytes) {
+  if (!s) return dd::set_error(DD_ERR_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (pending) *pending = static_cast<int32_t>(s->pending.size());
+  if (inflight) *inflight = static_cast<int32_t>(s->inflight.size());
+  if (finished) *finished = static_cast<int32_t>(s->done.size());
+  if (free_bytes) *free_bytes = s->dev_alloc.largest();
+  return DD_OK;
 }
+
+dd_status dd_serve_destroy(dd_server* s) {
+  delete s;
+  return DD_OK;
+}
+
+}  // extern "C"
