@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput benchmark: brute-force de-dispersion on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload scale_f32]
+    python bench.py [--steps K] [--warmup W] [--workload scale_f32] [--only]
 
 One step is one dd_execute over the whole workload (every DM trial, every
 output sample, all channels), with the input already resident in HBM.
@@ -15,23 +15,43 @@ Workloads (synthetic, seeded; see synth/):
   scale_u8       the same data quantised to 8 bits (128 + 16x), int32 out
   scale_f16      the same data in binary16, f32 out
   tiny_f32       64 ch 400-432 MHz, 8192 samples, 128 DMs (launch-bound)
+  batch_u8       32 beams of uneven shapes (256-1024 ch, 2^16-2^18 samples,
+                 1024-4096 DMs), 8-bit noise + 4 pulses each, one persistent
+                 graph-captured launch per step
+  serve_u8       64 streaming beams, 2048 ch 120-180 MHz, 327.68 us, 4096 DMs
+                 step 0.125, chunks of 2^14-2^17 samples arriving as Poisson
+                 processes at 1.5x real time; p50/p99 latency, RTF
+
+By default (scale_f32) the line also carries "precision" (u8 and f16 on the
+same data, with their error and the S/N of the injected pulses), "batch" and
+"serve" blocks; --only drops them.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import synth  # noqa: E402
+
 # Peak rates (MI355X, 256 CUs at 2.4 GHz).  The de-dispersion kernels are
 # bound by plain VALU adds: 128 32-bit adds per clock per CU
 # (= 157.3 TFLOP/s FP32 vector counted as 2 flops per FMA) = 78.6e12 adds/s.
 PEAK_ADD_PER_S = 256 * 2.4e9 * 128
 PEAK_HBM_BPS = 8.0e12
+
+# rocprofv3 FETCH_SIZE / WRITE_SIZE of the dominant kernel per launch
+# (KiB, scaled by the plain-copy calibration), keyed by workload.  Each entry
+# names the kernel source hash it was taken with; it is reported only while
+# the source is unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def parse():
@@ -40,43 +60,119 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale_f32",
-                    choices=["scale_f32", "scale_u8", "scale_f16", "tiny_f32"])
+                    choices=["scale_f32", "scale_u8", "scale_f16", "tiny_f32", "batch_u8",
+                             "serve_u8"])
+    ap.add_argument("--only", action="store_true",
+                    help="time only the named workload (no precision/batch/serve blocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the paced (1.5x real time) serving window")
+    ap.add_argument("--serve-saturate", type=int, default=128,
+                    help="chunks in the unpaced (saturating) serving phase")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run one plain 1 GiB device copy (for scaling "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
 
 
-def make_workload(name):
-    """Seeded synthetic input for `name`.  Pulse arrival offsets come from the
-    oracle's delay routine (the CPU-baseline leg times the oracle on this
-    same input)."""
-    import oracle
-    import synth
-    if name.startswith("scale"):
-        w = synth.scale()
-    else:
-        w = synth.tiny()
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_1107_2516_amd")
+    for f in ("csrc/dd_kernels.hip", "csrc/gen_window_asm.py", "csrc/dd_internal.h",
+              "csrc/dd_plan.cpp", "build.py"):
+        with open(os.path.join(pkg, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, launches_per_step=1):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = tab.get(workload)
+    if not e or e.get("kernel_source") != kernel_source_hash():
+        return None
+    return {"fetch_bytes": e["fetch_bytes"], "write_bytes": e["write_bytes"],
+            "per": "launch", "copy_factor": e.get("copy_factor"), "source": e.get("profile")}
+
+
+def timed(stream, fn, steps, warmup):
+    """Run fn() warmup times, then time `steps` calls: HIP events on the
+    launch stream and the host wall clock, both bracketed by syncs."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / steps, wall * 1e3 / steps
+
+
+def roofline(adds, in_bytes, out_bytes, kernel_ms, unit, traffic=None):
+    achieved = adds / (kernel_ms * 1e-3)
+    alg_bytes = in_bytes + out_bytes
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ADD_PER_S / 1e12,
+            "unit": unit, "frac": achieved / PEAK_ADD_PER_S, "traffic": traffic,
+            "kernel_ms": kernel_ms, "alg_adds_per_launch": adds,
+            "alg_bytes_per_launch": alg_bytes,
+            "hbm_gbs_algorithmic": alg_bytes / (kernel_ms * 1e-3) / 1e9,
+            "hbm_frac_algorithmic": alg_bytes / (kernel_ms * 1e-3) / PEAK_HBM_BPS}
+
+
+def pulse_offsets(dd, band, dm):
+    """Per-channel arrival offsets of a pulse at `dm`: row 0 of the library's
+    delay table for a one-trial plan."""
+    p = dd.Plan(band.nchans, band.f_top, band.df, band.t_samp, [dm])
+    return p.delay_table()[0]
+
+
+# --------------------------------------------------------------------------
+# Single-beam workloads (scale_*, tiny_f32)
+# --------------------------------------------------------------------------
+
+
+def make_workload(dd, name):
+    """Seeded synthetic input and its plan."""
+    w = synth.scale() if name.startswith("scale") else synth.tiny()
     b = w.band
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
     x = synth.noise(b.nchans, w.nsamp, w.seed)
+    pulses = []
     if name.startswith("scale"):
-        tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
-        nout = w.nsamp - oracle.max_shift(tab)
-        for p in synth.scale_pulses(w.seed, w.extra["npulses"], nout):
-            off = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, [p["dm"]])[0]
-            synth.add_boxcar(x, off, p["t0"], p["width"], p["amp"])
+        nout = w.nsamp - plan.max_shift
+        pulses = synth.scale_pulses(w.seed, w.extra["npulses"], nout)
     else:
-        tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
         e = w.extra
-        synth.add_boxcar(x, tab[50], e["pulse_t0"], e["pulse_width"], e["pulse_amp"])
-    if name.endswith("u8"):
-        x = synth.quantize_u8(x)
-    elif name.endswith("f16"):
-        x = synth.to_f16(x)
-    return w, x
+        pulses = [dict(dm=float(w.dms[50]), width=e["pulse_width"], amp=e["pulse_amp"],
+                       t0=e["pulse_t0"], snr=None)]
+    for p in pulses:
+        synth.add_boxcar(x, pulse_offsets(dd, b, p["dm"]), p["t0"], p["width"], p["amp"])
+    return w, plan, x, pulses
+
+
+def convert(x, dt):
+    if dt == "u8":
+        return synth.quantize_u8(x)
+    if dt == "f16":
+        return synth.to_f16(x)
+    return x
 
 
 def describe(name, w):
@@ -89,12 +185,52 @@ def describe(name, w):
             f"{w.dms[1] - w.dms[0]:g}, N(0,1) noise + injected pulses, {dt}")
 
 
-def cpu_baseline(x, w, ndms, nout, budget_s):
-    """The oracle (plain C, FP64/int64 accumulation, OpenMP over DM rows) on
-    a bounded sample of DM rows over the full time range."""
+def run_single(dd, torch, plan, w, xh, dt, args):
+    dev = torch.device("cuda:0")
+    nsamp = w.nsamp
+    nout = plan.nout(nsamp)
+    xin = torch.from_numpy(xh).to(dev)
+    out = torch.empty((plan.ndms, nout), dtype=dd.out_dtype_for(xin.dtype), device=dev)
+    stream = torch.cuda.current_stream(dev)
+    kms, wall_ms = timed(stream, lambda: plan.execute(xin, out=out), args.steps, args.warmup)
+    adds = float(plan.ndms) * plan.nchans * nout
+    unit = "TOP/s" if dt == "u8" else "TFLOP/s"
+    rl = roofline(adds, float(plan.nchans) * nsamp * xh.dtype.itemsize,
+                  float(plan.ndms) * nout * 4, kms, unit)
+    return {"kernel_ms": kms, "ms_per_step": wall_ms, "value": plan.ndms * nout / (wall_ms * 1e-3),
+            "roofline": rl, "tile": plan.tile_for(xin.dtype, nsamp),
+            "real_time_factor": (kms * 1e-3) / (nout * w.band.t_samp)}, out
+
+
+def boxcar_snr_peak(row, t0, width, search=64):
+    """Peak boxcar S/N of a de-dispersed row near output sample t0, with the
+    row's median and 1.4826*MAD as baseline and scale."""
+    x = np.asarray(row, dtype=np.float64)
+    mu = np.median(x)
+    sigma = 1.482602218505602 * np.median(np.abs(x - mu))
+    lo, hi = max(0, t0 - search), min(x.size, t0 + width + search)
+    c = np.concatenate([[0.0], np.cumsum(x[lo:hi] - mu)])
+    box = c[width:] - c[:-width]
+    return float(box.max() / (sigma * math.sqrt(width)))
+
+
+def pulse_snrs(out, w, pulses):
+    step = float(w.dms[1] - w.dms[0])
+    rows = [int(min(len(w.dms) - 1, round(p["dm"] / step))) for p in pulses]
+    host = out[rows].float().cpu().numpy()
+    return [boxcar_snr_peak(host[i], p["t0"], p["width"]) for i, p in enumerate(pulses)]
+
+
+def cpu_baseline(w, xs, outs, budget_s):
+    """The oracle (plain C, FP64/int64 accumulation, OpenMP over DM rows)
+    timed on a bounded sample of DM rows over the full time range, and the
+    GPU results of every precision compared with it on those rows."""
     import oracle
     b = w.band
     tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
+    ndms = tab.shape[0]
+    x = xs["f32"]
+    nout = x.shape[1] - int(tab.max())
     threads = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
@@ -108,12 +244,281 @@ def cpu_baseline(x, w, ndms, nout, budget_s):
     nrows = max(threads, (nrows // threads) * threads)
     rows = np.linspace(0, ndms - 1, nrows).astype(np.int32)
     t0 = time.perf_counter()
-    oracle.dedisperse(x, tab, rows=rows, nthreads=threads)
+    ref = oracle.dedisperse(x, tab, rows=rows, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": nrows * nout / dt, "unit": "DM-trial samples/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{nrows} of {ndms} DM rows x {nout} output samples x {b.nchans} channels "
-                      f"({dt:.1f} s on {threads} threads)"}
+    res = {"value": nrows * nout / dt, "unit": "DM-trial samples/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{nrows} of {ndms} DM rows x {nout} output samples x {b.nchans} channels "
+                     f"({dt:.1f} s on {threads} threads)"}
+    # accuracy of each GPU result on (up to) 16 of the sampled rows
+    sub = np.unique(np.linspace(0, nrows - 1, min(nrows, 16)).astype(np.int64))
+    r_rows = rows[sub]
+    ref_rows = ref[sub]
+    den = oracle.dedisperse(np.abs(x), tab, rows=r_rows, nthreads=threads)
+    acc = {"rows_checked": int(len(r_rows))}
+    for dt_name, out in outs.items():
+        y = out[torch_index(r_rows)].cpu().numpy().astype(np.float64)
+        if dt_name == "u8":
+            exact = oracle.dedisperse(xs["u8"], tab, rows=r_rows, nthreads=threads)
+            acc["u8"] = {"bit_exact_vs_oracle": bool(np.array_equal(y.astype(np.int64), exact)),
+                         "rel_err_vs_fp64_f32_input": normwise(
+                             (y - 128.0 * b.nchans) / 16.0, ref_rows)}
+        elif dt_name == "f16":
+            same = oracle.dedisperse(xs["f16"], tab, rows=r_rows, nthreads=threads)
+            dsame = oracle.dedisperse(np.abs(xs["f16"]), tab, rows=r_rows, nthreads=threads)
+            acc["f16"] = {"scaled_err_vs_oracle": float(np.max(np.abs(y - same) / dsame)),
+                          "rel_err_vs_fp64_f32_input": normwise(y, ref_rows)}
+        else:
+            acc["f32"] = {"scaled_err_vs_oracle": float(np.max(np.abs(y - ref_rows) / den)),
+                          "rel_err_vs_fp64_f32_input": normwise(y, ref_rows)}
+    res["accuracy"] = acc
+    return res
+
+
+def torch_index(rows):
+    import torch
+    return torch.from_numpy(np.asarray(rows, dtype=np.int64)).cuda()
+
+
+def normwise(y, ref):
+    return float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+# --------------------------------------------------------------------------
+# Many beams in one persistent launch
+# --------------------------------------------------------------------------
+
+
+def run_batch(dd, torch, args):
+    dev = torch.device("cuda:0")
+    specs = synth.batch_beams()
+    plans, pulses = [], []
+    for sp in specs:
+        bd = sp["band"]
+        p = dd.Plan(bd.nchans, bd.f_top, bd.df, bd.t_samp, synth.dm_grid(sp["ndms"], sp["step"]))
+        plans.append(p)
+        nout = p.nout(sp["nsamp"])
+        dm_max = float(sp["ndms"] - 1) * sp["step"] * 0.98
+        ps = synth.scale_pulses(sp["seed"], 4, nout, dm_max=dm_max, nchans=bd.nchans)
+        pulses.append([(pulse_offsets(dd, bd, q["dm"]), q) for q in ps])
+
+    def gen(i):
+        sp = specs[i]
+        x = synth.noise(sp["band"].nchans, sp["nsamp"], sp["seed"])
+        for off, q in pulses[i]:
+            synth.add_boxcar(x, off, q["t0"], q["width"], q["amp"])
+        return synth.quantize_u8(x)
+
+    log("batch: generating 32 beams")
+    xs = []
+    with ThreadPoolExecutor(8) as ex:
+        for u8 in ex.map(gen, range(len(specs))):
+            xs.append(torch.from_numpy(u8).to(dev))
+    bt = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    tuned = None
+    if not args.no_autotune:
+        cfg, ms = bt.autotune()
+        tuned = {"tile": cfg, "ms": ms}
+    info = bt.info()
+    stream = torch.cuda.current_stream(dev)
+    steps = max(1, min(args.steps, 10))
+    kms, wall_ms = timed(stream, lambda: bt.launch(), steps, max(1, min(args.warmup, 2)))
+    samples = sum(p.ndms * p.nout(x.shape[1]) for p, x in zip(plans, xs))
+    adds = float(sum(p.ndms * p.nchans * p.nout(x.shape[1]) for p, x in zip(plans, xs)))
+    in_bytes = float(sum(x.numel() for x in xs))
+    # the same beams one dd_execute at a time (no batching, no graph)
+    def one_by_one():
+        for p, x, o in zip(plans, xs, bt.outputs):
+            p.execute(x, out=o)
+    seq_ms, seq_wall = timed(stream, one_by_one, 1, 1)
+    res = {"beams": len(specs), "kernel_ms": kms, "ms_per_step": wall_ms,
+           "value": samples / (wall_ms * 1e-3), "unit": "DM-trial samples/s",
+           "dm_trial_samples_per_step": samples, "work_items": info["work_items"],
+           "grid": info["grid"], "tile": info["tile"], "autotune": tuned,
+           "unbatched_ms": seq_wall, "speedup_vs_unbatched": seq_wall / wall_ms,
+           "roofline": roofline(adds, in_bytes, samples * 4.0, kms, "TOP/s")}
+    del bt, xs
+    torch.cuda.empty_cache()
+    return res
+
+
+# --------------------------------------------------------------------------
+# Streaming beams (continuous batching server)
+# --------------------------------------------------------------------------
+
+
+def run_serve(dd, torch, args, nbeams=64):
+    dev = torch.device("cuda:0")
+    band = synth.serve_band()
+    seed = 2518
+    plan = dd.Plan(band.nchans, band.f_top, band.df, band.t_samp, synth.dm_grid(4096, 0.125))
+    m = plan.max_shift
+    max_chunk = 1 << 17
+    period = 1 << 18  # each beam streams a periodic noise buffer, phase-shifted per beam
+    assert period > m
+    log("serve: generating the noise buffer")
+    pool = synth.noise(band.nchans, period, seed)
+    for q in synth.serve_pulses(seed, 16, period, nchans=band.nchans):
+        synth.add_boxcar_cyclic(pool, pulse_offsets(dd, band, q["dm"]), q["t0"], q["width"],
+                                q["amp"])
+    pool = synth.quantize_u8(pool)
+    # a second period appended so that any chunk is one column slice
+    pool = np.concatenate([pool, pool[:, :max_chunk]], axis=1)
+    g = synth.rng(seed + 2)
+    phase = [int(v) for v in g.integers(0, period, nbeams)]
+
+    carry = (m + max_chunk) * band.nchans
+    out_max = plan.ndms * ((max_chunk + 63) // 64 * 64) * 4
+    max_inflight, nstreams = 8, 4
+    arena_bytes = nbeams * carry + nstreams * m * band.nchans + 2 * max_inflight * out_max + (1 << 30)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    srv = dd.Server(arena, torch.uint8, max_inflight=max_inflight, queue_capacity=512,
+                    nstreams=nstreams, host_staging_bytes=4 << 30)
+    beams = [srv.add_beam(plan, max_chunk) for _ in range(nbeams)]
+    pos = [0] * nbeams
+    seq = [0] * nbeams
+    stalls = {"n": 0}
+
+    def submit(b, n):
+        s = (phase[b] + pos[b]) % period
+        while True:
+            tk = srv.submit(beams[b], pool[:, s:s + n], seq[b])
+            if tk is not None:
+                pos[b] += n
+                seq[b] += 1
+                return tk
+            stalls["n"] += 1
+            drain_some(block=True)
+
+    done = {}
+
+    def drain_some(block=False):
+        got = 0
+        while True:
+            rs = srv.poll(256)
+            for r in rs:
+                if r.status != dd.DD_OK:
+                    raise RuntimeError(f"chunk {r.ticket} failed: {dd.status_str(r.status)}")
+                done[r.ticket] = r
+                srv.release(r.ticket)
+            got += len(rs)
+            if got or not block:
+                return got
+            time.sleep(2e-4)
+
+    def wait_all(tickets):
+        while not all(t in done for t in tickets):
+            drain_some(block=True)
+
+    # warm-up: every beam needs max_shift samples of history before its first output
+    log(f"serve: warming {nbeams} beams ({m} samples each)")
+    t_w = time.perf_counter()
+    warm = []
+    for b in range(nbeams):
+        left = m
+        while left > 0:
+            n = min(left, max_chunk)
+            warm.append(submit(b, n))
+            left -= n
+    wait_all(warm)
+    warm_s = time.perf_counter() - t_w
+
+    # paced phase: Poisson arrivals at 1.5x real time
+    mean_len = (2.0 ** 17 - 2.0 ** 14) / (math.log(2.0) * 3.0)
+    per_beam = int(math.ceil(args.serve_seconds * 1.5 / (mean_len * band.t_samp) * 2)) + 4
+    events = [e for e in synth.serve_arrivals(seed, nbeams, per_beam * nbeams, band.t_samp, 1.5)
+              if e[0] < args.serve_seconds]
+    log(f"serve: paced phase, {len(events)} chunks over {args.serve_seconds:g} s")
+    sched = {}
+    t_start = time.monotonic() + 0.2
+    stalls["n"] = 0
+    for (t_arr, b, _, n) in events:
+        due = t_start + t_arr
+        while True:
+            now = time.monotonic()
+            if now >= due:
+                break
+            if not drain_some():
+                time.sleep(min(5e-4, due - now))
+        tk = submit(b, n)
+        sched[tk] = (due, n)
+    wait_all(list(sched))
+    paced_wall = time.monotonic() - t_start
+    lat = np.array([done[t].t_done - sched[t][0] for t in sched])
+    compute = np.array([done[t].t_done - done[t].t_admit for t in sched])
+    paced_samples = sum(n for _, n in sched.values())
+    paced_stalls = stalls["n"]
+
+    # saturating phase: a backlog of chunks submitted as fast as admission allows
+    g2 = synth.rng(seed + 3)
+    lens = [int(math.floor(2.0 ** g2.uniform(14.0, 17.0))) for _ in range(args.serve_saturate)]
+    order = [int(v) for v in g2.integers(0, nbeams, args.serve_saturate)]
+    log(f"serve: saturating phase, {len(lens)} chunks")
+    stalls["n"] = 0
+    t0 = time.monotonic()
+    sat = [submit(b, n) for b, n in zip(order, lens)]
+    wait_all(sat)
+    sat_wall = time.monotonic() - t0
+    sat_samples = float(sum(lens))
+    sat_lat = np.array([done[t].t_done - done[t].t_submit for t in sat])
+    srv.close()
+
+    # the plain kernel at the serving shape (carry + one maximum chunk)
+    xk = torch.from_numpy(np.ascontiguousarray(pool[:, :m + max_chunk])).to(dev)
+    ok = torch.empty((plan.ndms, max_chunk), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    kms, _ = timed(stream, lambda: plan.execute(xk, out=ok), 5, 1)
+    kernel_rate = plan.ndms * max_chunk / (kms * 1e-3)
+    adds = float(plan.ndms) * plan.nchans * max_chunk
+
+    obs = paced_samples * band.t_samp / nbeams
+    return {
+        "beams": nbeams, "nchans": band.nchans, "ndms": plan.ndms, "max_shift": m,
+        "chunk_samples": [1 << 14, max_chunk], "arrival_rate_x_realtime": 1.5,
+        "warmup_s": warm_s,
+        "paced": {"window_s": args.serve_seconds, "chunks": len(sched),
+                  "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                  "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                  "max_ms": float(lat.max() * 1e3),
+                  "p50_gpu_ms": float(np.percentile(compute, 50) * 1e3),
+                  "wall_s": paced_wall, "observation_s_per_beam": obs,
+                  "admission_stalls": paced_stalls,
+                  "value": paced_samples * plan.ndms / paced_wall},
+        "saturated": {"chunks": len(sat), "wall_s": sat_wall,
+                      "value": sat_samples * plan.ndms / sat_wall,
+                      "unit": "DM-trial samples/s",
+                      "real_time_factor": sat_wall / (sat_samples * band.t_samp / nbeams),
+                      "p50_ms": float(np.percentile(sat_lat, 50) * 1e3),
+                      "p99_ms": float(np.percentile(sat_lat, 99) * 1e3),
+                      "admission_stalls": stalls["n"]},
+        "kernel_at_chunk_shape": {"kernel_ms": kms, "value": kernel_rate,
+                                  "roofline": roofline(adds, float(xk.numel()),
+                                                       plan.ndms * max_chunk * 4.0, kms,
+                                                       "TOP/s")},
+        "served_over_kernel": (sat_samples * plan.ndms / sat_wall) / kernel_rate,
+    }
+
+
+# --------------------------------------------------------------------------
+
+
+def base_line(args, metric_value, ms_per_step, dtype, config, rl):
+    return {
+        "metric": "DM-trial samples/s",
+        "value": metric_value,
+        "unit": "DM-trial samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+        "roofline": rl,
+    }
 
 
 def main():
@@ -126,65 +531,74 @@ def main():
     import paper_1107_2516_amd as dd
 
     name = args.workload
-    w, x = make_workload(name)
-    b = w.band
-    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
-    ndms, nsamp = plan.ndms, w.nsamp
-    nout = plan.nout(nsamp)
-    dev = torch.device("cuda:0")
-    xin = torch.from_numpy(x).to(dev)
-    out = torch.empty((ndms, nout), dtype=dd.out_dtype_for(xin.dtype), device=dev)
-    stream = torch.cuda.current_stream(dev)
+    if name == "batch_u8":
+        r = run_batch(dd, torch, args)
+        r["roofline"]["traffic"] = traffic_for(name)
+        line = base_line(args, r["value"], r["ms_per_step"], "u8",
+                         {"workload": "batch_u8: 32 beams, 256-1024 ch 1214-1510 MHz, 64 us, "
+                                      "2^16-2^18 samples, 1024-4096 DMs, u8 noise + 4 pulses "
+                                      "each, one persistent graph-captured launch",
+                          "beams": r["beams"]}, r.pop("roofline"))
+        line["batch"] = r
+        print(json.dumps(line), flush=True)
+        return
+    if name == "serve_u8":
+        r = run_serve(dd, torch, args)
+        line = base_line(args, r["saturated"]["value"], r["saturated"]["wall_s"] * 1e3, "u8",
+                         {"workload": "serve_u8: 64 beams, 2048 ch 120-180 MHz, 327.68 us, 4096 "
+                                      "DMs step 0.125, Poisson chunks of 2^14-2^17 samples at "
+                                      "1.5x real time"},
+                         r["kernel_at_chunk_shape"].pop("roofline"))
+        line["roofline"]["traffic"] = traffic_for(name)
+        line["serve"] = r
+        print(json.dumps(line), flush=True)
+        return
 
-    for _ in range(args.warmup):
-        plan.execute(xin, out=out)
-    torch.cuda.synchronize(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize(dev)
-    t_wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.execute(xin, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize(dev)
-    t_wall = time.perf_counter() - t_wall0
-    gpu_ms = ev0.elapsed_time(ev1) / args.steps
-    ms_per_step = t_wall * 1e3 / args.steps
-
-    b_in = x.dtype.itemsize
-    adds = float(ndms) * b.nchans * nout
-    alg_bytes = float(b.nchans) * nsamp * b_in + float(ndms) * nout * 4
-    achieved = adds / (gpu_ms * 1e-3)
-    unit = "TOP/s" if name.endswith("u8") else "TFLOP/s"
-    line = {
-        "metric": "DM-trial samples/s",
-        "value": ndms * nout / (ms_per_step * 1e-3),
-        "unit": "DM-trial samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"f32": "f32", "u8": "u8", "f16": "f16"}[name.rsplit("_", 1)[1]],
-        "data": "synthetic",
-        "config": {"workload": describe(name, w), "nchans": b.nchans, "ndms": ndms,
-                   "nsamp": nsamp, "nout": nout, "max_shift": plan.max_shift,
-                   "tile": plan.tile_for(xin.dtype, nsamp)},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ADD_PER_S / 1e12,
-                     "unit": unit, "frac": achieved / PEAK_ADD_PER_S, "traffic": None,
-                     "kernel_ms": gpu_ms, "alg_adds_per_launch": adds,
-                     "alg_bytes_per_launch": alg_bytes,
-                     "hbm_gbs_algorithmic": alg_bytes / (gpu_ms * 1e-3) / 1e9,
-                     "hbm_frac_algorithmic": alg_bytes / (gpu_ms * 1e-3) / PEAK_HBM_BPS},
-        "real_time_factor": (gpu_ms * 1e-3) / (nout * b.t_samp),
-    }
+    w, plan, x32, pulses = make_workload(dd, name)
+    dt = name.rsplit("_", 1)[1]
+    xs = {dt: convert(x32, dt)}
+    log(f"{name}: timing")
+    main_r, main_out = run_single(dd, torch, plan, w, xs[dt], dt, args)
+    main_r["roofline"]["traffic"] = traffic_for(name)
+    cfg = {"workload": describe(name, w), "nchans": w.band.nchans, "ndms": plan.ndms,
+           "nsamp": w.nsamp, "nout": plan.nout(w.nsamp), "max_shift": plan.max_shift,
+           "tile": main_r["tile"]}
+    line = base_line(args, main_r["value"], main_r["ms_per_step"], dt, cfg, main_r["roofline"])
+    line["real_time_factor"] = main_r["real_time_factor"]
+    outs = {dt: main_out}
+    extras = name == "scale_f32" and not args.only
+    if extras:
+        prec = {"f32": {"value": main_r["value"], "kernel_ms": main_r["kernel_ms"],
+                        "frac": main_r["roofline"]["frac"],
+                        "hbm_gbs_algorithmic": main_r["roofline"]["hbm_gbs_algorithmic"],
+                        "pulse_snr": pulse_snrs(main_out, w, pulses)}}
+        for pdt in ("u8", "f16"):
+            log(f"precision {pdt}: timing")
+            xs[pdt] = convert(x32, pdt)
+            r, o = run_single(dd, torch, plan, w, xs[pdt], pdt, args)
+            outs[pdt] = o
+            prec[pdt] = {"value": r["value"], "kernel_ms": r["kernel_ms"],
+                         "frac": r["roofline"]["frac"], "tile": r["tile"],
+                         "hbm_gbs_algorithmic": r["roofline"]["hbm_gbs_algorithmic"],
+                         "speedup_vs_f32": main_r["kernel_ms"] / r["kernel_ms"],
+                         "pulse_snr": pulse_snrs(o, w, pulses)}
+        prec["injected_snr"] = [p["snr"] for p in pulses]
+        line["precision"] = prec
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(x, w, ndms, nout, args.cpu_seconds)
+        if "f32" not in xs:
+            xs["f32"] = x32
+        log("cpu baseline: timing the oracle")
+        line["cpu_baseline"] = cpu_baseline(w, xs, outs, args.cpu_seconds)
         line["cpu_baseline"]["gpu_over_cpu"] = line["value"] / line["cpu_baseline"]["value"]
+    del outs, main_out
+    torch.cuda.empty_cache()
+    if extras:
+        log("batch: start")
+        line["batch"] = run_batch(dd, torch, args)
+        log("serve: start")
+        line["serve"] = run_serve(dd, torch, args)
     if args.copy_calibration:
+        dev = torch.device("cuda:0")
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         src.fill_(1.0)
         dst = torch.empty_like(src)

@@ -245,7 +245,9 @@ dd_status dd_serve_add_beam(dd_server* srv, const dd_plan* plan, int64_t max_chu
 
 /*
  * Queue one chunk: nsamp samples of every channel, host memory laid out
- * [nchans][nsamp].  The chunk is copied into the server's pinned staging pool
+ * [nchans][in_stride] (in_stride >= nsamp elements between the starts of
+ * consecutive channel rows; only the first nsamp of each row are read).
+ * The chunk is copied into the server's pinned staging pool
  * before this call returns.  seq must increase by one per beam; a gap
  * restarts the beam (its carry is dropped and it warms up again).  Chunks of
  * one beam must be submitted from one thread at a time.
@@ -254,7 +256,7 @@ dd_status dd_serve_add_beam(dd_server* srv, const dd_plan* plan, int64_t max_chu
  * DD_ERR_NOT_FOUND for an unknown beam.
  */
 dd_status dd_serve_submit(dd_server* srv, int32_t beam, const void* h_chunk, int64_t nsamp,
-                          int64_t seq, uint64_t* ticket);
+                          int64_t in_stride, int64_t seq, uint64_t* ticket);
 
 /* Collect up to `max` finished chunks (non-blocking). */
 dd_status dd_serve_poll(dd_server* srv, dd_result* out, int32_t max, int32_t* n);

@@ -101,7 +101,7 @@ _SIGS = {
     "dd_tile_for": [_P, ctypes.c_int, _I64, ctypes.POINTER(TileConfig)],
     "dd_serve_create": [ctypes.POINTER(ServeConfig), _P, ctypes.c_size_t, _PP],
     "dd_serve_add_beam": [_P, _P, _I64, ctypes.POINTER(_I32)],
-    "dd_serve_submit": [_P, _I32, _P, _I64, _I64, ctypes.POINTER(ctypes.c_uint64)],
+    "dd_serve_submit": [_P, _I32, _P, _I64, _I64, _I64, ctypes.POINTER(ctypes.c_uint64)],
     "dd_serve_poll": [_P, ctypes.POINTER(Result), _I32, ctypes.POINTER(_I32)],
     "dd_serve_release": [_P, ctypes.c_uint64],
     "dd_serve_drain": [_P],
@@ -386,12 +386,15 @@ class Server:
         return b.value
 
     def submit(self, beam, chunk: np.ndarray, seq):
-        """Queue a host chunk [nchans, nsamp] (C-contiguous numpy array).
+        """Queue a host chunk [nchans, nsamp] (numpy array whose rows are
+        contiguous; rows may be a stride apart, e.g. a column slice).
         Returns the ticket, or None when the server is full (DD_ERR_AGAIN)."""
-        c = np.ascontiguousarray(chunk)
+        c = chunk
+        if c.ndim != 2 or c.strides[1] != c.itemsize or c.strides[0] % c.itemsize:
+            c = np.ascontiguousarray(c)
         t = ctypes.c_uint64()
-        st = lib().dd_serve_submit(self._h, int(beam), c.ctypes.data, int(c.shape[1]), int(seq),
-                                   ctypes.byref(t))
+        st = lib().dd_serve_submit(self._h, int(beam), c.ctypes.data, int(c.shape[1]),
+                                   int(c.strides[0] // c.itemsize), int(seq), ctypes.byref(t))
         if st == DD_ERR_AGAIN:
             return None
         _check(st)

@@ -383,9 +383,10 @@ dd_status dd_serve_add_beam(dd_server* s, const dd_plan* plan, int64_t max_chunk
 }
 
 dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64_t nsamp,
-                          int64_t seq, uint64_t* ticket) {
+                          int64_t in_stride, int64_t seq, uint64_t* ticket) {
   try {
     if (!s || !h_chunk || !ticket) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+    if (in_stride < nsamp) return dd::set_error(DD_ERR_INVALID_ARG, "in_stride < nsamp");
     const double t = dd::now_s();
     std::unique_lock<std::mutex> lk(s->mu);
     if (beam < 0 || beam >= static_cast<int32_t>(s->beams.size()))
@@ -415,7 +416,16 @@ dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64
     b.next_seq = seq + 1;
     b.pending++;
     lk.unlock();
-    std::memcpy(s->pinned + off, h_chunk, bytes);  // outside the lock; the chunk is not queued yet
+    // outside the lock; the chunk is not queued yet
+    if (in_stride == nsamp) {
+      std::memcpy(s->pinned + off, h_chunk, bytes);
+    } else {
+      const size_t row = static_cast<size_t>(nsamp) * s->esize;
+      const size_t pitch = static_cast<size_t>(in_stride) * s->esize;
+      const char* src = static_cast<const char*>(h_chunk);
+      for (int32_t c = 0; c < b.plan->nchans; c++)
+        std::memcpy(s->pinned + off + c * row, src + c * pitch, row);
+    }
     lk.lock();
     *ticket = c->ticket;
     s->pending.push_back(c.release());

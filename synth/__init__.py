@@ -103,9 +103,34 @@ def add_boxcar(data: np.ndarray, offsets, t0: int, width: int, amp: float) -> No
             data[c, max(a, 0):b] += np.asarray(amp, dtype=data.dtype)
 
 
+def add_boxcar_cyclic(data: np.ndarray, offsets, t0: int, width: int, amp: float) -> None:
+    """As add_boxcar, for a buffer that is read as a periodic stream: sample
+    indices wrap modulo the buffer length."""
+    nchans, nsamp = data.shape
+    offsets = np.asarray(offsets, dtype=np.int64)
+    cols = np.arange(int(width), dtype=np.int64)
+    for c in range(nchans):
+        data[c, (int(t0) + int(offsets[c]) + cols) % nsamp] += np.asarray(amp, dtype=data.dtype)
+
+
 def quantize_u8(x: np.ndarray) -> np.ndarray:
-    """8-bit samples: clip(rint(128 + 16 x), 0, 255)."""
-    return np.clip(np.rint(128.0 + 16.0 * np.asarray(x, dtype=np.float64)), 0, 255).astype(np.uint8)
+    """8-bit samples: clip(rint(128 + 16 x), 0, 255), evaluated in FP64
+    (rint rounds half to even).  Large arrays are converted in row blocks on
+    a few threads; every element gets the same arithmetic."""
+    x = np.asarray(x)
+    out = np.empty(x.shape, dtype=np.uint8)
+
+    def conv(sl):
+        out[sl] = np.clip(np.rint(128.0 + 16.0 * x[sl].astype(np.float64)), 0, 255)
+
+    if x.ndim < 2 or x.size < (1 << 22):
+        conv(slice(None))
+        return out
+    from concurrent.futures import ThreadPoolExecutor
+    step = max(1, x.shape[0] // 32)
+    with ThreadPoolExecutor(8) as ex:
+        list(ex.map(conv, [slice(i, i + step) for i in range(0, x.shape[0], step)]))
+    return out
 
 
 def to_f16(x: np.ndarray) -> np.ndarray:
@@ -172,3 +197,19 @@ def serve_arrivals(seed: int, nbeams: int, nchunks: int, t_samp: float, rate: fl
             events.append((t, b, s, n))
     events.sort()
     return events
+
+
+def serve_pulses(seed: int, npulses: int, period: int, dm_max: float = 500.0,
+                 max_width: int = 64, snr_range=(10.0, 40.0), nchans: int = 2048):
+    """Pulse draws for the streaming workload's periodic noise buffer: DM ~
+    U[0, dm_max], width ~ U{1..max_width}, target S/N ~ U[snr_range],
+    amplitude S/N / sqrt(nchans * width), t0 ~ U{0..period-1}."""
+    g = rng(seed + 1)
+    out = []
+    for _ in range(npulses):
+        dm = float(g.uniform(0.0, dm_max))
+        w = int(g.integers(1, max_width + 1))
+        s = float(g.uniform(*snr_range))
+        out.append(dict(dm=dm, width=w, snr=s, amp=s / math.sqrt(nchans * w),
+                        t0=int(g.integers(0, period))))
+    return out
