@@ -313,7 +313,11 @@ def run_batch(dd, torch, args):
     xs = []
     with ThreadPoolExecutor(8) as ex:
         for u8 in ex.map(gen, range(len(specs))):
-            xs.append(torch.from_numpy(u8).to(dev))
+            # rows start on 64-byte boundaries (pitched allocation)
+            pitch = (u8.shape[1] + 63) // 64 * 64
+            buf = torch.empty((u8.shape[0], pitch), dtype=torch.uint8, device=dev)
+            buf[:, :u8.shape[1]].copy_(torch.from_numpy(u8))
+            xs.append(buf[:, :u8.shape[1]])
     bt = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
     tuned = None
     if not args.no_autotune:
@@ -325,7 +329,7 @@ def run_batch(dd, torch, args):
     kms, wall_ms = timed(stream, lambda: bt.launch(), steps, max(1, min(args.warmup, 2)))
     samples = sum(p.ndms * p.nout(x.shape[1]) for p, x in zip(plans, xs))
     adds = float(sum(p.ndms * p.nchans * p.nout(x.shape[1]) for p, x in zip(plans, xs)))
-    in_bytes = float(sum(x.numel() for x in xs))
+    in_bytes = float(sum(x.shape[0] * x.shape[1] for x in xs))
     # the same beams one dd_execute at a time (no batching, no graph)
     def one_by_one():
         for p, x, o in zip(plans, xs, bt.outputs):

@@ -65,6 +65,8 @@ struct DeviceTables {
   std::map<int, TileTables> by_td;
   // aligned-copies offsets keyed by (td, samples per dword, dwords per copy)
   std::map<std::tuple<int, int, int>, int32_t*> aoff;
+  // rel + (base mod samples per dword), keyed by (td, samples per dword)
+  std::map<std::pair<int, int>, int32_t*> ralign;
 };
 
 }  // namespace dd
@@ -93,6 +95,9 @@ dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out);
 // a = base & (epd-1) and R = a + rel, the DM reads copy R mod epd at dword
 // R / epd, i.e. offset (R mod epd) * slotd + R / epd within the channel.
 dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** out);
+// Per (tile, channel, DM) shifts relative to the channel's window start
+// rounded down to a whole dword: rel + (base & (epd-1)).
+dd_status plan_ralign(dd_plan* plan, int td, int epd, const int32_t** out);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {

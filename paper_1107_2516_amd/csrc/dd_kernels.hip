@@ -29,6 +29,9 @@
 //  3  BodyCopies:  u8 / f16; EPD shifted copies of each staged channel so
 //                  every DM reads aligned dwords; u8 sums in 16-bit SWAR
 //                  lanes with fast VOP2 instructions, f16 with v_fma_mix.
+//  4  BodyWinX:    u8 / f16 through a register window: the staged rows are
+//                  expanded to one 32-bit word per sample (f16 -> FP32; u8 ->
+//                  two samples in 16-bit lanes, so one add sums two samples).
 #include <cstring>
 #include <type_traits>
 
@@ -40,8 +43,6 @@ namespace {
 #include "dd_window_asm.inc"
 
 typedef __attribute__((address_space(3))) void lds_void_t;
-typedef int int4v __attribute__((ext_vector_type(4)));
-typedef int int8v __attribute__((ext_vector_type(8)));
 
 struct KParams {
   const void* in;
@@ -55,44 +56,28 @@ struct KParams {
   int32_t n_dtiles, n_ttiles, nblocks, per_xcd;
 };
 
-// Wave-uniform loads through the scalar cache.  The tables are read-only for
-// the whole launch; the explicit s_load keeps them out of the vector memory
-// path even where the compiler cannot prove that no store aliases them.
-__device__ __forceinline__ int sload1(const int32_t* p) {
-  int v;
-  asm volatile("s_load_dword %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
-  return v;
+// The table pointers are wave-uniform by construction; readfirstlane states
+// it where the compiler's uniformity analysis cannot see it (it folds away
+// where it can).
+__device__ __forceinline__ const int32_t* uniform_ptr(const int32_t* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<const int32_t*>((static_cast<uint64_t>(hi) << 32) | lo);
 }
-template <int N>
-__device__ __forceinline__ void sload(const int32_t* p, int* r) {
-  static_assert(N == 4 || N == 8, "4 or 8 dwords");
-  if constexpr (N == 4) {
-    int4v v;
-    asm volatile("s_load_dwordx4 %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
-#pragma unroll
-    for (int i = 0; i < 4; i++) r[i] = v[i];
-  } else {
-    int8v v;
-    asm volatile("s_load_dwordx8 %0, %1, 0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
-#pragma unroll
-    for (int i = 0; i < 8; i++) r[i] = v[i];
-  }
+// Table reads through the constant address space: the compiler issues them as
+// scalar loads (the address is wave-uniform) and places the wait before the
+// first use, so a load issued one channel ahead hides its latency.
+typedef __attribute__((address_space(4))) const int32_t cint32_t;
+__device__ __forceinline__ const cint32_t* const_ptr(const int32_t* p) {
+  return (const cint32_t*)uniform_ptr(p);
 }
-// DW consecutive table entries (the tables are padded so that the
-// power-of-two over-read of the last wavefront stays inside them).
+__device__ __forceinline__ int cload1(const int32_t* p) { return *const_ptr(p); }
 template <int DW>
-__device__ __forceinline__ void sload_dw(const int32_t* p, int* r) {
-  if constexpr (DW <= 4) {
-    int t[4];
-    sload<4>(p, t);
+__device__ __forceinline__ void cload_dw(const int32_t* p, int* r) {
+  const cint32_t* q = const_ptr(p);
 #pragma unroll
-    for (int i = 0; i < DW; i++) r[i] = t[i];
-  } else {
-    int t[8];
-    sload<8>(p, t);
-#pragma unroll
-    for (int i = 0; i < DW; i++) r[i] = t[i];
-  }
+  for (int i = 0; i < DW; i++) r[i] = q[i];
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -120,7 +105,7 @@ struct Acc<uint8_t> {
 template <typename Tin, typename Tout, int DW, int K>
 struct BodyLds {
   static constexpr int TD = 4 * DW, TT = 64 * K, OCC = 2;
-  __device__ static void run(const KParams& p, int dtile, int ttile) {
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
     using TA = typename Acc<Tin>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     Tin* lds = reinterpret_cast<Tin*>(smem);
@@ -139,7 +124,7 @@ struct BodyLds {
       __syncthreads();
       for (int cc = 0; cc < ncc; cc++) {
         const int c = c0 + cc;
-        const int64_t g0 = t0 + sload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c);
+        const int64_t g0 = t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c);
         const Tin* src = in + static_cast<int64_t>(c) * p.in_stride;
         Tin* dst = lds + cc * p.slot;
         for (int j = tid; j < p.slot; j += 256) {
@@ -151,7 +136,7 @@ struct BodyLds {
       for (int cc = 0; cc < ncc; cc++) {
         const int c = c0 + cc;
         int r[DW];
-        sload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c) * TD + wave * DW, r);
+        cload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c) * TD + wave * DW, r);
         const Tin* row = lds + cc * p.slot + lane;
 #pragma unroll
         for (int d = 0; d < DW; d++) {
@@ -202,10 +187,11 @@ struct BodyLds {
 // issued before stage s is computed.  The buffer descriptor of each channel
 // row bounds reads at nsamp samples, so samples past the end read as zero
 // (they only feed outputs t >= nout, which are not stored).
-template <int DW, int K, int WMAX, int OCC_, void (*STEP)(float*, const int*, unsigned)>
+template <int DW, int K, int WMAX, int OCC_,
+          void (*STEP)(float*, const int*, unsigned, const int32_t*, int*)>
 struct BodyWin {
   static constexpr int TD = 4 * DW, TT = 64 * K, OCC = OCC_;
-  __device__ static void run(const KParams& p, int dtile, int ttile) {
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* lds = reinterpret_cast<float*>(smem);
     const int64_t t0 = static_cast<int64_t>(ttile) * TT;
@@ -224,7 +210,7 @@ struct BodyWin {
       for (int i = wave; i < ncc; i += 4) {
         const int c = c0 + i;
         const int g0 =
-            static_cast<int>(t0) + sload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c);
+            static_cast<int>(t0) + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c);
         __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float*>(in + static_cast<int64_t>(c) * p.in_stride), 0,
             static_cast<int>(row_bytes), 0x00020000);
@@ -237,6 +223,9 @@ struct BodyWin {
     float acc[DW * K];
 #pragma unroll
     for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
+    const int32_t* tabw = p.tab + static_cast<int64_t>(dtile) * p.nchans * TD + wave * DW;
+    int r[DW];
+    cload_dw<DW>(tabw, r);
     issue(0, 0);
     for (int s = 0; s < nstage; s++) {
       const int buf = s & 1;
@@ -246,9 +235,11 @@ struct BodyWin {
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
       for (int i = 0; i < ncc; i++) {
-        int r[DW];
-        sload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0 + i) * TD + wave * DW, r);
-        STEP(acc, r, lane_addr + static_cast<unsigned>((buf * cc_max + i) * slot * 4));
+        int rn[DW];  // next channel's shifts, loaded by the step behind its first DM
+        STEP(acc, r, lane_addr + static_cast<unsigned>((buf * cc_max + i) * slot * 4),
+             uniform_ptr(tabw + static_cast<int64_t>(min(c0 + i + 1, p.nchans - 1)) * TD), rn);
+#pragma unroll
+        for (int j = 0; j < DW; j++) r[j] = rn[j];
       }
     }
     float* out = static_cast<float*>(p.out);
@@ -306,7 +297,7 @@ struct BodyCopies {
   static constexpr int EPD = 4 / static_cast<int>(sizeof(Tin));
   static constexpr int SH = EPD == 4 ? 2 : 1;
   static constexpr int TD = 4 * DW, TT = 64 * I * EPD, OCC = OCC_;
-  __device__ static void run(const KParams& p, int dtile, int ttile) {
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* lds = reinterpret_cast<uint32_t*>(smem);
     const int64_t t0 = static_cast<int64_t>(ttile) * TT;
@@ -323,7 +314,7 @@ struct BodyCopies {
     const int chan_dw = EPD * slotd;  // LDS: [buffer][stage channel][copy][slotd]
     auto window_dword = [&](int c) -> int {
       return static_cast<int>(
-          (t0 + sload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
+          (t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
     };
     auto issue = [&](int s, int buf) {
       const int c0 = s * cc_max;
@@ -419,7 +410,7 @@ struct BodyCopies {
       const int ncc = min(cc_max, p.nchans - c0);
       for (int i = 0; i < ncc; i++) {
         int o[DW];
-        sload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0 + i) * TD + wave * DW, o);
+        cload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0 + i) * TD + wave * DW, o);
         const int chan_off = (buf * cc_max + i) * chan_dw;
         uint32_t xs[DW][I];
 #pragma unroll
@@ -492,6 +483,212 @@ struct BodyCopies {
   static constexpr int table_epd = EPD;
 };
 
+// ---------------------------------------------------------------- variant 4
+//
+// Register-window variant for 8-bit and half-precision input.  Raw rows are
+// staged by asynchronous buffer loads straight into LDS (double-buffered,
+// whole dwords from the channel's window start rounded down to a dword) and
+// then expanded once per stage into one 32-bit word per sample position,
+// which the register-window step reads:
+//  * f16: the sample converted to FP32; the step is the FP32 one.
+//  * u8:  sample s in the low and sample s+1 in the high 16 bits, so one
+//    32-bit add sums two samples into two 16-bit lanes (the pair step).  The
+//    lanes are emptied into the int32 output every 256 channels (stored the
+//    first time, added afterwards: the workgroup owns those outputs), which
+//    keeps them below 2^16 and needs no 32-bit copy of the sums in VGPRs.
+// The DM shifts come from the aligned-shift table (rel plus the window
+// start's offset inside its dword).
+template <typename Tin, int DW, int K, int WMAX, int OCC_, typename AccT,
+          void (*STEP)(AccT*, const int*, unsigned, const int32_t*, int*)>
+struct BodyWinX {
+  static constexpr bool U8 = sizeof(Tin) == 1;
+  static constexpr int EPD = 4 / static_cast<int>(sizeof(Tin));
+  static constexpr int SH = U8 ? 2 : 1;
+  static constexpr int TD = 4 * DW, TT = 64 * K, OCC = OCC_;
+  static constexpr int NACC = U8 ? DW * K / 2 : DW * K;
+  static constexpr int FLUSH = 256;
+  static_assert(K % 4 == 0, "window reads are 16-byte aligned");
+  // raw dwords per channel and buffer: the window's dwords plus the next one
+  // (u8 pairs straddle it), in whole 64-dword DMA instructions so that no
+  // wavefront's copy spills into the next channel's region
+  __host__ __device__ static constexpr int raw_dwords(int slot) {
+    return (slot / EPD + 1 + 63) & ~63;
+  }
+
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* xp = reinterpret_cast<uint32_t*>(smem);  // expanded: [channel][slot]
+    const int slot = p.slot;                            // samples per channel, multiple of 64
+    const int cc_max = p.cc;
+    const int rawd = raw_dwords(slot);
+    uint32_t* raw = xp + cc_max * slot;                 // raw: [buffer][channel][rawd]
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_id();
+    const unsigned char* in = static_cast<const unsigned char*>(p.in);
+    const int nstage = (p.nchans + cc_max - 1) / cc_max;
+    const int64_t row_bytes = p.in_stride * static_cast<int64_t>(sizeof(Tin));
+    const int full_dwords = static_cast<int>(p.nsamp / EPD);
+    const int tail = static_cast<int>(p.nsamp % EPD);
+    auto window_dword = [&](int c) -> int {
+      return static_cast<int>(
+          (t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
+    };
+    auto issue = [&](int s, int buf) {
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int gd = window_dword(c);
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char*>(in + static_cast<int64_t>(c) * row_bytes), 0,
+            full_dwords * 4, 0x00020000);
+        uint32_t* dst = raw + (buf * cc_max + i) * rawd;
+        for (int e = 0; e < rawd; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
+      }
+    };
+    // the partial dword at the end of row c, assembled from bytes (the buffer
+    // loads read whole dwords only and leave it at zero)
+    auto tail_dword = [&](int c) -> uint32_t {
+      const unsigned char* row =
+          in + static_cast<int64_t>(c) * row_bytes + static_cast<int64_t>(full_dwords) * 4;
+      uint32_t v = 0;
+      for (int k = 0; k < tail * static_cast<int>(sizeof(Tin)); k++)
+        v |= static_cast<uint32_t>(row[k]) << (8 * k);
+      return v;
+    };
+    auto build = [&](int s, int buf) {
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = 0; i < ncc; i++) {
+        const int c = c0 + i;
+        const uint32_t* src = raw + (buf * cc_max + i) * rawd;
+        uint32_t* dst = xp + i * slot;
+        const int tl = full_dwords - window_dword(c);  // raw index of the partial dword
+        for (int e = tid; e < slot / EPD; e += 256) {
+          uint32_t lo = src[e];
+          if (tail && e == tl) lo = tail_dword(c);
+          if constexpr (U8) {
+            uint32_t hi = src[e + 1];
+            if (tail && e + 1 == tl) hi = tail_dword(c);
+            uint4 v;
+            v.x = __builtin_amdgcn_perm(hi, lo, 0x0c010c00u);  // b0 | b1 << 16
+            v.y = __builtin_amdgcn_perm(hi, lo, 0x0c020c01u);  // b1 | b2 << 16
+            v.z = __builtin_amdgcn_perm(hi, lo, 0x0c030c02u);  // b2 | b3 << 16
+            v.w = __builtin_amdgcn_perm(hi, lo, 0x0c040c03u);  // b3 | b4 << 16
+            *reinterpret_cast<uint4*>(dst + 4 * e) = v;
+          } else {
+            _Float16 h0, h1;
+            const uint16_t u0 = static_cast<uint16_t>(lo & 0xffffu);
+            const uint16_t u1 = static_cast<uint16_t>(lo >> 16);
+            __builtin_memcpy(&h0, &u0, 2);
+            __builtin_memcpy(&h1, &u1, 2);
+            float2 f;
+            f.x = static_cast<float>(h0);
+            f.y = static_cast<float>(h1);
+            *reinterpret_cast<float2*>(dst + 2 * e) = f;
+          }
+        }
+      }
+    };
+
+    AccT acc[NACC];
+#pragma unroll
+    for (int i = 0; i < NACC; i++) acc[i] = AccT(0);
+    const int64_t tb = t0 + static_cast<int64_t>(lane) * K;
+    // u8: move the 16-bit lane sums into the int32 output and clear them
+    auto flush = [&](bool first) {
+      if constexpr (U8) {
+        int32_t* out = static_cast<int32_t*>(p.out);
+#pragma unroll
+        for (int j = 0; j < DW; j++) {
+          const int row = p.rows[dtile * TD + wave * DW + j];
+          if (row >= 0) {
+            int32_t* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+            for (int i = 0; i < K / 2; i++) {
+              const uint32_t a = acc[j * (K / 2) + i];
+              const int64_t t = tb + 2 * i;
+              const int32_t lo = static_cast<int32_t>(a & 0xffffu);
+              const int32_t hi = static_cast<int32_t>(a >> 16);
+              if (t < p.nout) o[t] = first ? lo : o[t] + lo;
+              if (t + 1 < p.nout) o[t + 1] = first ? hi : o[t + 1] + hi;
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < K / 2; i++) acc[j * (K / 2) + i] = 0;
+        }
+      }
+    };
+
+    const unsigned lane_addr = static_cast<unsigned>(reinterpret_cast<uintptr_t>(xp)) +
+                               static_cast<unsigned>(lane * K * 4);
+    int since = 0;
+    bool first = true;
+    const int32_t* tabw = p.tab + static_cast<int64_t>(dtile) * p.nchans * TD + wave * DW;
+    int r[DW];
+    cload_dw<DW>(tabw, r);
+    issue(0, 0);
+    for (int s = 0; s < nstage; s++) {
+      const int buf = s & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // raw stage s landed; every wave is done reading the expanded stage s-1
+      build(s, buf);
+      __syncthreads();  // expanded stage s ready
+      if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      for (int i = 0; i < ncc; i++) {
+        int rn[DW];  // next channel's shifts, loaded by the step behind its first DM
+        STEP(acc, r, lane_addr + static_cast<unsigned>(i * slot * 4),
+             uniform_ptr(tabw + static_cast<int64_t>(min(c0 + i + 1, p.nchans - 1)) * TD), rn);
+#pragma unroll
+        for (int j = 0; j < DW; j++) r[j] = rn[j];
+        if constexpr (U8) {
+          if (++since == FLUSH) {
+            flush(first);
+            first = false;
+            since = 0;
+          }
+        }
+      }
+    }
+    if constexpr (U8) {
+      if (since || first) flush(first);
+    } else {
+      float* out = static_cast<float*>(p.out);
+#pragma unroll
+      for (int j = 0; j < DW; j++) {
+        const int row = p.rows[dtile * TD + wave * DW + j];
+        if (row < 0) continue;
+        float* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+          const int64_t t = tb + k;
+          if (t < p.nout) o[t] = acc[j * K + k];
+        }
+      }
+    }
+  }
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    const int s = (TT + span_max + (EPD - 1) + WMAX + 63) & ~63;
+    const size_t per_chan = static_cast<size_t>(s) * 4 + 2 * static_cast<size_t>(raw_dwords(s)) * 4;
+    const size_t budget = 160 * 1024 / OCC;
+    if (per_chan > budget) return -1;
+    int c = cc_req;
+    while (c > 1 && per_chan * c > budget) c--;
+    *slot = s;
+    *cc = c;
+    *lds = per_chan * c;
+    return 0;
+  }
+  static constexpr int table_epd = 0;
+  static constexpr int table_ralign = EPD;
+};
+
 // ------------------------------------------------------------------ kernels
 
 template <class Body>
@@ -555,9 +752,18 @@ struct Impl {
   int (*geometry)(int span_max, int cc_req, int* slot, int* cc, size_t* lds);
   const void* single;
   const void* batch;
-  int td, tt, table_epd;
+  int td, tt, table_epd, table_ralign;
   size_t in_size;
   bool needs_dword_rows;
+};
+
+template <class Body, class = void>
+struct RalignOf {
+  static constexpr int value = 0;
+};
+template <class Body>
+struct RalignOf<Body, std::void_t<decltype(Body::table_ralign)>> {
+  static constexpr int value = Body::table_ralign;
 };
 
 template <class Body, typename Tin>
@@ -569,8 +775,9 @@ Impl make_impl() {
   m.td = Body::TD;
   m.tt = Body::TT;
   m.table_epd = Body::table_epd;
+  m.table_ralign = RalignOf<Body>::value;
   m.in_size = sizeof(Tin);
-  m.needs_dword_rows = Body::table_epd != 0;
+  m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0;
   return m;
 }
 
@@ -606,6 +813,31 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
     if (d == 8 && k == 8) return *out = make_impl<BodyCopies<uint8_t, 8, 2, 4>, uint8_t>(), true;
     if (d == 4 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 4, 4, 4>, uint8_t>(), true;
     if (d == 8 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 8, 4, 2>, uint8_t>(), true;
+  }
+  if (in_t == DD_U8 && v == 4) {
+    if (d == 8 && k == 28)
+      return *out = make_impl<BodyWinX<uint8_t, 8, 28, 84, 2, uint32_t, dd_u8p_d8_k28_w84_channel>,
+                              uint8_t>(), true;
+    if (d == 8 && k == 20)
+      return *out = make_impl<BodyWinX<uint8_t, 8, 20, 56, 3, uint32_t, dd_u8p_d8_k20_w56_channel>,
+                              uint8_t>(), true;
+    if (d == 4 && k == 28)
+      return *out = make_impl<BodyWinX<uint8_t, 4, 28, 64, 3, uint32_t, dd_u8p_d4_k28_w64_channel>,
+                              uint8_t>(), true;
+  }
+  if (in_t == DD_F16 && v == 4) {
+    if (d == 8 && k == 12)
+      return *out = make_impl<BodyWinX<_Float16, 8, 12, 48, 3, float, dd_f32_d8_k12_w48_channel>,
+                              _Float16>(), true;
+    if (d == 8 && k == 20)
+      return *out = make_impl<BodyWinX<_Float16, 8, 20, 56, 2, float, dd_f32_d8_k20_w56_channel>,
+                              _Float16>(), true;
+    if (d == 4 && k == 20)
+      return *out = make_impl<BodyWinX<_Float16, 4, 20, 56, 3, float, dd_f32_d4_k20_w56_channel>,
+                              _Float16>(), true;
+    if (d == 4 && k == 12)
+      return *out = make_impl<BodyWinX<_Float16, 4, 12, 40, 4, float, dd_f32_d4_k12_w40_channel>,
+                              _Float16>(), true;
   }
   if (in_t == DD_F16 && v == 3) {
     if (d == 8 && k == 8) return *out = make_impl<BodyCopies<_Float16, 8, 4, 4>, _Float16>(), true;
@@ -647,6 +879,9 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
   const int32_t* tab = tt->d_rel;
   if (impl.table_epd) {
     st = plan_aoff(a.plan, impl.td, impl.table_epd, slot, &tab);
+    if (st != DD_OK) return st;
+  } else if (impl.table_ralign) {
+    st = plan_ralign(a.plan, impl.td, impl.table_ralign, &tab);
     if (st != DD_OK) return st;
   }
   const int64_t n_ttiles = (a.nout + impl.tt - 1) / impl.tt;

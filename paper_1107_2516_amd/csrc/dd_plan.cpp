@@ -204,6 +204,50 @@ dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** o
   return DD_OK;
 }
 
+dd_status plan_ralign(dd_plan* plan, int td, int epd, const int32_t** out) {
+  const TileTables* tt = nullptr;
+  dd_status st = plan_tiles(plan, td, &tt);
+  if (st != DD_OK) return st;
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceTables& dt = plan->dev[dev];
+  const auto key = std::make_pair(td, epd);
+  auto it = dt.ralign.find(key);
+  if (it != dt.ralign.end()) {
+    *out = it->second;
+    return DD_OK;
+  }
+  const int nch = plan->nchans;
+  const int ntiles = tt->ntiles;
+  std::vector<int32_t> host(static_cast<size_t>(ntiles) * nch * td + 8, 0);
+  for (int tile = 0; tile < ntiles; tile++) {
+    const int first = tile * td;
+    const int count = std::min(td, plan->ndms - first);
+    for (int c = 0; c < nch; c++) {
+      int32_t lo = INT32_MAX;
+      for (int j = 0; j < count; j++)
+        lo = std::min(lo, plan->delays[static_cast<size_t>(plan->order[first + j]) * nch + c]);
+      for (int j = 0; j < td; j++) {
+        const int src = plan->order[first + (j < count ? j : 0)];
+        host[(static_cast<size_t>(tile) * nch + c) * td + j] =
+            (lo & (epd - 1)) + plan->delays[static_cast<size_t>(src) * nch + c] - lo;
+      }
+    }
+  }
+  int32_t* d = nullptr;
+  hipError_t e = hipMalloc(&d, host.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(d, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_error(e, "uploading aligned shifts");
+  }
+  dt.ralign.emplace(key, d);
+  *out = d;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 dd_plan::~dd_plan() {
@@ -217,6 +261,7 @@ dd_plan::~dd_plan() {
       (void)hipFree(t.second.d_rows);
     }
     for (auto& t : kv.second.aoff) (void)hipFree(t.second);
+    for (auto& t : kv.second.ralign) (void)hipFree(t.second);
     (void)hipSetDevice(cur);
   }
 }

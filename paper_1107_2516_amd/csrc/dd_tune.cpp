@@ -62,8 +62,9 @@ std::vector<TileShape> candidates(dd_dtype in_t) {
             make(1, 4, 12, 8), make(2, 8, 12, 8), make(0, 8, 8, 8)};
   if (in_t == DD_U8)
     return {make(3, 8, 8, 8), make(3, 8, 8, 4), make(3, 4, 16, 8), make(3, 8, 16, 4),
-            make(0, 8, 8, 8)};
-  return {make(3, 8, 8, 8), make(3, 8, 4, 8), make(0, 8, 8, 8)};
+            make(4, 8, 20, 8), make(4, 8, 28, 8), make(4, 4, 28, 8), make(0, 8, 8, 8)};
+  return {make(3, 8, 8, 8), make(3, 8, 4, 8), make(4, 8, 12, 8), make(4, 8, 20, 6),
+          make(0, 8, 8, 8)};
 }
 
 TileShape builtin_default(dd_dtype in_t) {

@@ -18,6 +18,8 @@ Per DM j the block:
   * reloads the window (WMAX/4 ds_read_b128) when r_j falls outside the
     current one (start aligned down to 4 samples),
   * runs K v_add_f32 with SRC0 indexed by r_j - start.
+After the first DM the step issues the scalar load of the next channel's
+shifts (`next`, returned in `rn`); it completes behind the remaining DMs.
 """
 import sys
 
@@ -37,6 +39,25 @@ def vgpr_budget(occ):
     return min(256, (512 // occ) // 8 * 8)
 
 
+def prefetch_decl(dw):
+    """Locals of a channel step, including the SGPR tuple that receives the
+    next channel's shifts."""
+    vec = "int4v" if dw <= 4 else "int8v"
+    return ["  int ws, ix, tb;", "  unsigned va;", f"  {vec} nv;"]
+
+
+def prefetch_issue(dw):
+    """The next channel's shifts are loaded once the first DM's window has
+    arrived, so the channel's only mandatory LDS wait does not also wait for
+    this scalar load; the step ends with a wait for it."""
+    op = "s_load_dwordx4" if dw <= 4 else "s_load_dwordx8"
+    return f'      "{op} %[rn], %[tp], 0\\n"'
+
+
+def prefetch_store(dw):
+    return [f"  for (int i = 0; i < {dw}; i++) rn[i] = nv[i];"]
+
+
 def gen(name, dw, k, wmax, occ):
     assert k % 4 == 0 and wmax % 4 == 0 and wmax >= k + 4
     # the window sits at the top of the wave's VGPR budget so the kernel's
@@ -47,9 +68,8 @@ def gen(name, dw, k, wmax, occ):
     out.append(f"#define DD_{name.upper()}_DW {dw}")
     out.append(f"#define DD_{name.upper()}_K {k}")
     out.append(f"#define DD_{name.upper()}_WMAX {wmax}")
-    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* r, unsigned addr) {{")
-    out.append("  int ws, ix, tb;")
-    out.append("  unsigned va;")
+    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* r, unsigned addr, const int32_t* next, int* rn) {{")
+    out += prefetch_decl(dw)
     out.append("  asm volatile(")
     out.append('      "s_mov_b32 %[ws], 0x80000000\\n"')
     for j in range(dw):
@@ -70,16 +90,21 @@ def gen(name, dw, k, wmax, occ):
         for kk in range(k):
             out.append(f'      "v_add_f32 %[a{j}_{kk}], v{wb + kk}, %[a{j}_{kk}]\\n"')
         out.append('      "s_set_gpr_idx_off\\n"')
+        if j == 0:
+            out.append(prefetch_issue(dw))
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
     outs = []
     for j in range(dw):
         for kk in range(k):
             outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
-    outs += ['[ws] "=&s"(ws)', '[ix] "=&s"(ix)', '[tb] "=&s"(tb)', '[va] "=&v"(va)']
-    ins = ['[addr] "v"(addr)'] + [f'[r{j}] "s"(r[{j}])' for j in range(dw)]
+    outs += ['[ws] "=&s"(ws)', '[ix] "=&s"(ix)', '[tb] "=&s"(tb)', '[va] "=&v"(va)',
+             '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)'] + [f'[r{j}] "s"(r[{j}])' for j in range(dw)]
     clob = [f'"v{wb + i}"' for i in range(wmax)] + ['"m0"', '"scc"', '"memory"']
     out.append("      : " + ",\n        ".join(outs))
     out.append("      : " + ", ".join(ins))
     out.append("      : " + ", ".join(clob) + ");")
+    out += prefetch_store(dw)
     out.append("}")
     return "\n".join(out)
 
@@ -108,9 +133,8 @@ def gen_jt(name, dw, k, wmax, occ):
     out = []
     out.append(f"// {name}: DW={dw} K={k} WMAX={wmax} OCC={occ}, window v{wb}..v{wb + wmax - 1}, "
                f"{nv} blocks of {bs} bytes per DM")
-    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* r, unsigned addr) {{")
-    out.append("  int ws, ix, tb;")
-    out.append("  unsigned va;")
+    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* r, unsigned addr, const int32_t* next, int* rn) {{")
+    out += prefetch_decl(dw)
     out.append("  asm volatile(")
     out.append('      "s_mov_b32 %[ws], 0x80000000\\n"')
     out.append(f'      "s_getpc_b64 s[{PC_LO}:{PC_HI}]\\n"')
@@ -140,17 +164,87 @@ def gen_jt(name, dw, k, wmax, occ):
                 out.append(f'      "v_add_f32_e32 %[a{j}_{kk}], v{wb + ix + kk}, %[a{j}_{kk}]\\n"')
             out.append(f'      "s_branch .Lnext_%=_{j}\\n"')
         out.append(f'      ".Lnext_%=_{j}:\\n"')
+        if j == 0:
+            out.append(prefetch_issue(dw))
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
     outs = []
     for j in range(dw):
         for kk in range(k):
             outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
-    outs += ['[ws] "=&s"(ws)', '[ix] "=&s"(ix)', '[tb] "=&s"(tb)', '[va] "=&v"(va)']
-    ins = ['[addr] "v"(addr)'] + [f'[r{j}] "s"(r[{j}])' for j in range(dw)]
+    outs += ['[ws] "=&s"(ws)', '[ix] "=&s"(ix)', '[tb] "=&s"(tb)', '[va] "=&v"(va)',
+             '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)'] + [f'[r{j}] "s"(r[{j}])' for j in range(dw)]
     clob = [f'"v{wb + i}"' for i in range(wmax)] + [f'"s{i}"' for i in (PC_LO, PC_HI, T_LO, T_HI)]
     clob += ['"scc"', '"memory"']
     out.append("      : " + ",\n        ".join(outs))
     out.append("      : " + ", ".join(ins))
     out.append("      : " + ", ".join(clob) + ");")
+    out += prefetch_store(dw)
+    out.append("}")
+    return "\n".join(out)
+
+
+PAIR_CONFIGS = [
+    # 8-bit input as 16-bit sample pairs: name, DMs per wave, samples per lane,
+    # window registers, waves per SIMD
+    ("u8p_d8_k28_w84", 8, 28, 84, 2),
+    ("u8p_d8_k20_w76", 8, 20, 76, 2),
+    ("u8p_d8_k20_w56", 8, 20, 56, 3),
+    ("u8p_d4_k28_w64", 4, 28, 64, 3),
+]
+
+
+def gen_pairs(name, dw, k, wmax, occ):
+    """Pair flavour for 8-bit input.  The staged window holds one dword per
+    sample position s: sample s in the low 16 bits and sample s+1 in the high
+    16 bits.  A lane owns K consecutive outputs as K/2 accumulators, each two
+    16-bit sums (outputs 2i and 2i+1), so one v_add_u32 adds two samples, and
+    DM j reads window dwords ix_j + 2i.  No 16-bit lane can carry into its
+    neighbour as long as the caller empties the accumulators at least every
+    257 channels (257 * 255 < 2^16)."""
+    assert k % 4 == 0 and wmax % 4 == 0 and wmax >= k + 4
+    wb = vgpr_budget(occ) - wmax
+    na = k // 2
+    lim = wmax - k + 1  # largest ix with ix + 2*(na-1) inside the window
+    out = []
+    out.append(f"// {name}: DW={dw} K={k} WMAX={wmax} OCC={occ}, window v{wb}..v{wb + wmax - 1}")
+    out.append(f"__device__ __forceinline__ void dd_{name}_channel(uint32_t* acc, const int* r, unsigned addr, const int32_t* next, int* rn) {{")
+    out += prefetch_decl(dw)
+    out.append("  asm volatile(")
+    out.append('      "s_mov_b32 %[ws], 0x80000000\\n"')
+    for j in range(dw):
+        out.append(f'      "s_sub_u32 %[ix], %[r{j}], %[ws]\\n"')
+        out.append(f'      "s_cmp_gt_u32 %[ix], {lim}\\n"')
+        out.append(f'      "s_cbranch_scc0 .Lkeep_%=_{j}\\n"')
+        out.append(f'      "s_and_b32 %[ws], %[r{j}], -4\\n"')
+        out.append(f'      "s_sub_u32 %[ix], %[r{j}], %[ws]\\n"')
+        out.append('      "s_lshl_b32 %[tb], %[ws], 2\\n"')
+        out.append('      "v_add_u32 %[va], %[tb], %[addr]\\n"')
+        for i in range(wmax // 4):
+            off = f" offset:{16 * i}" if i else ""
+            out.append(f'      "ds_read_b128 v[{wb + 4 * i}:{wb + 4 * i + 3}], %[va]{off}\\n"')
+        out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+        out.append(f'      ".Lkeep_%=_{j}:\\n"')
+        out.append('      "s_set_gpr_idx_on %[ix], gpr_idx(SRC0)\\n"')
+        out.append('      "s_nop 0\\n"')
+        for i in range(na):
+            out.append(f'      "v_add_u32 %[a{j}_{i}], v{wb + 2 * i}, %[a{j}_{i}]\\n"')
+        out.append('      "s_set_gpr_idx_off\\n"')
+        if j == 0:
+            out.append(prefetch_issue(dw))
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+    outs = []
+    for j in range(dw):
+        for i in range(na):
+            outs.append(f'[a{j}_{i}] "+v"(acc[{j * na + i}])')
+    outs += ['[ws] "=&s"(ws)', '[ix] "=&s"(ix)', '[tb] "=&s"(tb)', '[va] "=&v"(va)',
+             '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)'] + [f'[r{j}] "s"(r[{j}])' for j in range(dw)]
+    clob = [f'"v{wb + i}"' for i in range(wmax)] + ['"m0"', '"scc"', '"memory"']
+    out.append("      : " + ",\n        ".join(outs))
+    out.append("      : " + ", ".join(ins))
+    out.append("      : " + ", ".join(clob) + ");")
+    out += prefetch_store(dw)
     out.append("}")
     return "\n".join(out)
 
@@ -158,11 +252,16 @@ def gen_jt(name, dw, k, wmax, occ):
 def main():
     print("// Generated by gen_window_asm.py; do not edit by hand.")
     print("#pragma once")
+    print("typedef int int4v __attribute__((ext_vector_type(4)));")
+    print("typedef int int8v __attribute__((ext_vector_type(8)));")
     for cfg in CONFIGS:
         print(gen(*cfg))
         print()
     for cfg in JT_CONFIGS:
         print(gen_jt(*cfg))
+        print()
+    for cfg in PAIR_CONFIGS:
+        print(gen_pairs(*cfg))
         print()
 
 

@@ -208,17 +208,26 @@ TILES_COPIES = [
     ("u8", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=4)),
     ("f16", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)),
     ("f16", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=4, chans_per_stage=8)),
+    ("u8", dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=28, chans_per_stage=8)),
+    ("u8", dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=8)),
+    ("u8", dict(variant=4, dms_per_wave=4, waves=4, tsamp_per_lane=28, chans_per_stage=4)),
+    ("f16", dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8)),
+    ("f16", dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6)),
+    ("f16", dict(variant=4, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=8)),
+    ("f16", dict(variant=4, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4)),
 ]
 
 
 @pytest.mark.parametrize("dtype,tile", TILES_COPIES,
-                         ids=[f"{d}_d{t['dms_per_wave']}_k{t['tsamp_per_lane']}" for d, t in TILES_COPIES])
+                         ids=[f"{d}_v{t['variant']}_d{t['dms_per_wave']}_k{t['tsamp_per_lane']}"
+                              for d, t in TILES_COPIES])
 @pytest.mark.parametrize("nsamp", [3001, 3002, 3003, 3004, 700])
 def test_copies_kernel(dtype, tile, nsamp):
-    """The aligned-copies kernel for 8-bit and half input: every shift residue
-    modulo the samples per dword, rows whose length is not a whole number of
-    dwords (the partial last dword is patched from global memory), more than
-    256 channels (the 16-bit lane flush), ragged DM and time tiles."""
+    """The 8-bit / half kernels (aligned copies, expanded register window):
+    every shift residue modulo the samples per dword, rows whose length is not
+    a whole number of dwords (the partial last dword is patched from global
+    memory), more than 256 channels (the 16-bit lane flush), ragged DM and
+    time tiles."""
     g = np.random.default_rng(nsamp + len(dtype))
     nchans, ndms = 300, 70
     tab = np.sort(rand_table(g, ndms, nchans, 280 if nsamp > 1000 else 150), axis=0)
@@ -238,6 +247,27 @@ def test_copies_kernel(dtype, tile, nsamp):
     else:
         e, _ = scaled_error(y, x, tab)
         assert e <= FP_TOL, e
+
+
+@pytest.mark.parametrize("tsamp,dw", [(28, 8), (20, 8), (28, 4)])
+def test_pair_window_flushes(tsamp, dw):
+    """8-bit register window over 1000 channels (16-bit lanes emptied into the
+    output after channels 256, 512, 768 and at the end): full-scale samples
+    everywhere but a random patch, so every lane sum reaches 255*256 before
+    its flush; a spread of shifts that forces window reloads."""
+    g = np.random.default_rng(500 + tsamp + dw)
+    nchans, ndms, nsamp = 1000, 45, 5003
+    tab = np.sort(rand_table(g, ndms, nchans, 900), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    x = np.full((nchans, nsamp), 255, dtype=np.uint8)
+    x[::7, 1000:1600] = g.integers(0, 256, size=x[::7, 1000:1600].shape, dtype=np.uint8)
+    stride = (nsamp + 3) // 4 * 4
+    big = np.zeros((nchans, stride), dtype=np.uint8)
+    big[:, :nsamp] = x
+    tile = dict(variant=4, dms_per_wave=dw, waves=4, tsamp_per_lane=tsamp, chans_per_stage=8)
+    y = plan.execute_tiled(torch.from_numpy(big).cuda()[:, :nsamp], tile)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().astype(np.int64), oracle.dedisperse(x, tab))
 
 
 @pytest.mark.parametrize("dtype", ["u8", "f16"])
