@@ -312,6 +312,8 @@ struct BodyCopies {
     const int full_dwords = static_cast<int>(p.nsamp / EPD);  // dwords wholly inside a row
     const int tail = static_cast<int>(p.nsamp % EPD);         // samples in the partial dword
     const int chan_dw = EPD * slotd;  // LDS: [buffer][stage channel][copy][slotd]
+    const int tabd = table_dwords(cc_max);  // then [buffer][stage channel][TD] offsets
+    int32_t* tabl = reinterpret_cast<int32_t*>(lds + 2 * cc_max * chan_dw);
     auto window_dword = [&](int c) -> int {
       return static_cast<int>(
           (t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
@@ -329,6 +331,16 @@ struct BodyCopies {
         for (int e = 0; e < slotd; e += 64)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
               rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
+      }
+      // the stage's copy offsets, [channel][TD], staged beside the data
+      if (wave == 3) {
+        const int32_t* t0p = p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0) * TD;
+        __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int32_t*>(t0p), 0, ncc * TD * 4, 0x00020000);
+        int32_t* dst = tabl + buf * tabd;
+        for (int e = 0; e < ncc * TD; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rt, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(e + lane) * 4u, 0, 0, 0);
       }
     };
     // The partial dword at the end of row c, assembled from bytes (the buffer
@@ -408,9 +420,15 @@ struct BodyCopies {
       if (s + 1 < nstage) issue(s + 1, buf ^ 1);
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
+      const int32_t* tb = tabl + buf * tabd + wave * DW;
+      int o[DW];
+#pragma unroll
+      for (int j = 0; j < DW; j++) o[j] = tb[j];
       for (int i = 0; i < ncc; i++) {
-        int o[DW];
-        cload_dw<DW>(p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0 + i) * TD + wave * DW, o);
+        int on[DW];  // next channel's offsets: an LDS read issued behind this channel's
+        const int32_t* tn = tb + min(i + 1, ncc - 1) * TD;
+#pragma unroll
+        for (int j = 0; j < DW; j++) on[j] = tn[j];
         const int chan_off = (buf * cc_max + i) * chan_dw;
         uint32_t xs[DW][I];
 #pragma unroll
@@ -444,6 +462,8 @@ struct BodyCopies {
             since_flush = 0;
           }
         }
+#pragma unroll
+        for (int j = 0; j < DW; j++) o[j] = on[j];
       }
     }
     flush();
@@ -472,14 +492,18 @@ struct BodyCopies {
     const int s = (64 * I + (span_max + EPD - 1 + EPD - 1) / EPD + 1 + 63) & ~63;
     const size_t per_chan = static_cast<size_t>(s) * 4 * EPD * 2;
     const size_t budget = 160 * 1024 / OCC;
-    if (per_chan > budget) return -1;
+    auto total = [&](int c) { return per_chan * c + 2 * static_cast<size_t>(table_dwords(c)) * 4; };
+    if (total(1) > budget) return -1;
     int c = cc_req;
-    while (c > 1 && per_chan * c > budget) c--;
+    while (c > 1 && total(c) > budget) c--;
     *slot = s;
     *cc = c;
-    *lds = per_chan * c;
+    *lds = total(c);
     return 0;
   }
+  // LDS dwords for one buffer of a stage's copy offsets, whole 64-dword
+  // DMA instructions
+  __host__ __device__ static constexpr int table_dwords(int cc) { return (cc * TD + 63) & ~63; }
   static constexpr int table_epd = EPD;
 };
 
