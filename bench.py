@@ -378,6 +378,9 @@ def run_serve(dd, torch, args, nbeams=64):
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     srv = dd.Server(arena, torch.uint8, max_inflight=max_inflight, queue_capacity=512,
                     nstreams=nstreams, host_staging_bytes=4 << 30)
+    # tile shape for this plan at the largest carry + chunk length (remembered
+    # by the library for every execute of that size class)
+    tuned_tile, tuned_ms = plan.autotune(torch.uint8, m + max_chunk)
     beams = [srv.add_beam(plan, max_chunk) for _ in range(nbeams)]
     pos = [0] * nbeams
     seq = [0] * nbeams
@@ -478,6 +481,7 @@ def run_serve(dd, torch, args, nbeams=64):
     obs = paced_samples * band.t_samp / nbeams
     return {
         "beams": nbeams, "nchans": band.nchans, "ndms": plan.ndms, "max_shift": m,
+        "tile": tuned_tile,
         "chunk_samples": [1 << 14, max_chunk], "arrival_rate_x_realtime": 1.5,
         "warmup_s": warm_s,
         "paced": {"window_s": args.serve_seconds, "chunks": len(sched),

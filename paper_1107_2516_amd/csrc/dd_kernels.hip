@@ -288,8 +288,9 @@ struct BodyWin {
 // Accumulation:
 //  * u8: SWAR in fast VOP2 instructions: e = x & 0x00ff00ff and
 //    o = (x >> 8) & 0x00ff00ff each hold two samples in 16-bit lanes and are
-//    added into 16-bit-lane accumulators, flushed into 32-bit sums every 256
-//    channels (255 * 256 < 2^16, so no lane ever carries).
+//    added into 16-bit-lane accumulators, emptied into the int32 output every
+//    256 channels (255 * 256 < 2^16, so no lane ever carries; the first time
+//    stored, then added: the workgroup owns those outputs).
 //  * f16: v_fma_mix_f32 (x * 1.0 + acc with x an f16 half; the product is
 //    exact), one instruction per sample, FP32 accumulation.
 template <typename Tin, int DW, int I, int OCC_>
@@ -377,7 +378,6 @@ struct BodyCopies {
 
     using AccT = typename std::conditional<EPD == 4, uint32_t, float>::type;
     AccT acc[DW][I][2];  // u8: even/odd 16-bit-lane pairs; f16: lo/hi halves
-    uint32_t tot[EPD == 4 ? DW : 1][EPD == 4 ? I : 1][4];
 #pragma unroll
     for (int j = 0; j < DW; j++)
 #pragma unroll
@@ -385,27 +385,35 @@ struct BodyCopies {
         acc[j][i][0] = AccT(0);
         acc[j][i][1] = AccT(0);
       }
-    if constexpr (EPD == 4) {
-#pragma unroll
-      for (int j = 0; j < DW; j++)
-#pragma unroll
-        for (int i = 0; i < I; i++)
-#pragma unroll
-          for (int k = 0; k < 4; k++) tot[j][i][k] = 0;
-    }
+    // u8: move the 16-bit lane sums into the int32 output (stored the first
+    // time, added afterwards: the workgroup owns these outputs) and clear them
+    bool first = true;
     auto flush = [&]() {
       if constexpr (EPD == 4) {
 #pragma unroll
-        for (int j = 0; j < DW; j++)
+        for (int j = 0; j < DW; j++) {
+          const int row = p.rows[dtile * TD + wave * DW + j];
+          if (row >= 0) {
+            int32_t* o = static_cast<int32_t*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
-          for (int i = 0; i < I; i++) {
-            tot[j][i][0] += acc[j][i][0] & 0xffffu;
-            tot[j][i][2] += acc[j][i][0] >> 16;
-            tot[j][i][1] += acc[j][i][1] & 0xffffu;
-            tot[j][i][3] += acc[j][i][1] >> 16;
-            acc[j][i][0] = 0;
-            acc[j][i][1] = 0;
+            for (int ii = 0; ii < I; ii++) {
+              const int64_t tb = t0 + 4 * static_cast<int64_t>(lane + 64 * ii);
+              const int32_t v[4] = {static_cast<int32_t>(acc[j][ii][0] & 0xffffu),
+                                    static_cast<int32_t>(acc[j][ii][1] & 0xffffu),
+                                    static_cast<int32_t>(acc[j][ii][0] >> 16),
+                                    static_cast<int32_t>(acc[j][ii][1] >> 16)};
+#pragma unroll
+              for (int k = 0; k < 4; k++)
+                if (tb + k < p.nout) o[tb + k] = first ? v[k] : o[tb + k] + v[k];
+            }
           }
+#pragma unroll
+          for (int ii = 0; ii < I; ii++) {
+            acc[j][ii][0] = 0;
+            acc[j][ii][1] = 0;
+          }
+        }
+        first = false;
       }
     };
 
@@ -466,21 +474,17 @@ struct BodyCopies {
         for (int j = 0; j < DW; j++) o[j] = on[j];
       }
     }
-    flush();
+    if constexpr (EPD == 4) {
+      if (since_flush || first) flush();
+    } else {
 #pragma unroll
-    for (int j = 0; j < DW; j++) {
-      const int row = p.rows[dtile * TD + wave * DW + j];
-      if (row < 0) continue;
+      for (int j = 0; j < DW; j++) {
+        const int row = p.rows[dtile * TD + wave * DW + j];
+        if (row < 0) continue;
+        float* o = static_cast<float*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
-      for (int ii = 0; ii < I; ii++) {
-        const int64_t tb = t0 + static_cast<int64_t>(EPD) * (lane + 64 * ii);
-        if constexpr (EPD == 4) {
-          int32_t* o = static_cast<int32_t*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
-#pragma unroll
-          for (int k = 0; k < 4; k++)
-            if (tb + k < p.nout) o[tb + k] = static_cast<int32_t>(tot[j][ii][k]);
-        } else {
-          float* o = static_cast<float*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+        for (int ii = 0; ii < I; ii++) {
+          const int64_t tb = t0 + static_cast<int64_t>(EPD) * (lane + 64 * ii);
           if (tb < p.nout) o[tb] = acc[j][ii][0];
           if (tb + 1 < p.nout) o[tb + 1] = acc[j][ii][1];
         }
@@ -728,8 +732,19 @@ __global__ __launch_bounds__(256, Body::OCC) void k_single(KParams p) {
 // x consumed first by the workgroups on XCD x (block b runs on XCD b mod 8)
 // through counter x, and afterwards by anyone (each workgroup tries the parts
 // in turn).  Every workgroup exits once all 8 parts are exhausted.
+// Occupancy of the persistent kernel: the body's own, except where the
+// work-fetch loop's extra live registers would make the body spill.
+template <class Body, class = void>
+struct BatchOcc {
+  static constexpr int value = Body::OCC;
+};
 template <class Body>
-__global__ __launch_bounds__(256, Body::OCC) void k_batch(const KParams* __restrict__ beams,
+struct BatchOcc<Body, std::void_t<decltype(Body::OCC_BATCH)>> {
+  static constexpr int value = Body::OCC_BATCH;
+};
+
+template <class Body>
+__global__ __launch_bounds__(256, BatchOcc<Body>::value) void k_batch(const KParams* __restrict__ beams,
                                                          const int32_t* __restrict__ first_item,
                                                          int32_t nbeams, int32_t total,
                                                          unsigned* __restrict__ counters) {
@@ -753,8 +768,10 @@ __global__ __launch_bounds__(256, Body::OCC) void k_batch(const KParams* __restr
       s_beam = beam;
     }
     __syncthreads();
-    const int item = s_item;
-    const int beam = s_beam;
+    // wave-uniform by construction; readfirstlane lets the compiler keep the
+    // beam's parameters in SGPRs
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    const int beam = __builtin_amdgcn_readfirstlane(s_beam);
     __syncthreads();  // s_item / s_beam are rewritten on the next pass
     if (item < 0) break;
     const KParams p = beams[beam];
@@ -834,7 +851,7 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
       return *out = make_impl<BodyWin<4, 20, 56, 3, dd_jt_f32_d4_k20_w56_channel>, float>(), true;
   }
   if (in_t == DD_U8 && v == 3) {
-    if (d == 8 && k == 8) return *out = make_impl<BodyCopies<uint8_t, 8, 2, 4>, uint8_t>(), true;
+    if (d == 8 && k == 8) return *out = make_impl<BodyCopies<uint8_t, 8, 2, 6>, uint8_t>(), true;
     if (d == 4 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 4, 4, 4>, uint8_t>(), true;
     if (d == 8 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 8, 4, 2>, uint8_t>(), true;
   }
