@@ -510,6 +510,21 @@ def run_serve(dd, torch, args, nbeams=64):
 # --------------------------------------------------------------------------
 
 
+def copy_calibration(torch, args):
+    """One plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB), the last
+    kernel of the run, for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE."""
+    if not args.copy_calibration:
+        return
+    dev = torch.device("cuda:0")
+    torch.cuda.empty_cache()
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize(dev)
+    dst.copy_(src)
+    torch.cuda.synchronize(dev)
+
+
 def base_line(args, metric_value, ms_per_step, dtype, config, rl):
     return {
         "metric": "DM-trial samples/s",
@@ -548,6 +563,7 @@ def main():
                                       "each, one persistent graph-captured launch",
                           "beams": r["beams"]}, r.pop("roofline"))
         line["batch"] = r
+        copy_calibration(torch, args)
         print(json.dumps(line), flush=True)
         return
     if name == "serve_u8":
@@ -559,6 +575,7 @@ def main():
                          r["kernel_at_chunk_shape"].pop("roofline"))
         line["roofline"]["traffic"] = traffic_for(name)
         line["serve"] = r
+        copy_calibration(torch, args)
         print(json.dumps(line), flush=True)
         return
 
@@ -605,14 +622,7 @@ def main():
         line["batch"] = run_batch(dd, torch, args)
         log("serve: start")
         line["serve"] = run_serve(dd, torch, args)
-    if args.copy_calibration:
-        dev = torch.device("cuda:0")
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        src.fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize(dev)
-        dst.copy_(src)  # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize(dev)
+    copy_calibration(torch, args)
     print(json.dumps(line), flush=True)
 
 
