@@ -13,6 +13,11 @@ What it computes (paper section and equation cited at each function):
                     FP64 accumulation (f32/f16/f64 inputs) or int64 (u8).
 * `snr`, `detect`   buffer statistics and an n-sigma threshold emitting
                     (time, DM, intensity) triplets, section 3 (output thread).
+* `detect_boxcar`   the detection stage after the path: per-row mean and
+                    standard deviation, boxcar sums of widths 1, 2, 4, ...,
+                    an n-sigma threshold on the best width of each sample,
+                    (DM row, time, width, S/N) events (section 3 output
+                    thread, with the boxcar matched filter of Figure 5).
 * `paper_maxshift`  the first-order maximum-shift bound of section 3
                     ("Maximum shift" equation), used only as a sanity bound.
 
@@ -199,3 +204,60 @@ def detect(out: np.ndarray, nsigma: float, dms=None):
     d_idx, t_idx = np.nonzero(x > mu + nsigma * sigma)
     dmv = d_idx if dms is None else np.asarray(dms)[d_idx]
     return list(zip(t_idx.tolist(), np.asarray(dmv).tolist(), x[d_idx, t_idx].tolist()))
+
+
+EVENT_DTYPE = np.dtype([("dm_row", np.int32), ("t", np.int64), ("width", np.int32),
+                        ("snr", np.float64)])
+
+
+def detect_boxcar(out: np.ndarray, nsigma: float, max_log2_width: int, rows=None) -> np.ndarray:
+    """Detection after de-dispersion (section 3's output thread normalises
+    the processed buffer and reports everything above an n-sigma threshold;
+    Figure 5 shows the boxcar-integrated S/N of a pulse).  Reading used:
+
+    * each DM row is normalised by its own mean mu_d and (population)
+      standard deviation sigma_d over all its samples, in FP64; a row with
+      sigma_d = 0 has no events;
+    * widths w = 2^k, k = 0..max_log2_width; the S/N of the box starting at
+      t is (sum_{i<w} x[d][t+i] - w*mu_d) / (sigma_d*sqrt(w)), defined for
+      t + w <= nout;
+    * sample (d, t) is an event when its best S/N over the defined widths is
+      >= nsigma; the event carries that S/N and its width (the smallest
+      width on ties).
+
+    Returns a structured array (EVENT_DTYPE) sorted by (dm_row, t)."""
+    x = np.asarray(out, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[None, :]
+    rows = np.arange(x.shape[0]) if rows is None else np.asarray(rows)
+    nout = x.shape[1]
+    found = []
+    for d in rows:
+        r = x[d]
+        mu = r.mean()
+        sigma = r.std()
+        if not sigma > 0.0:
+            continue
+        y = r - mu
+        c = np.concatenate([[0.0], np.cumsum(y)])
+        best = np.full(nout, -np.inf)
+        bw = np.zeros(nout, dtype=np.int32)
+        for k in range(max_log2_width + 1):
+            w = 1 << k
+            if w > nout:
+                break
+            s = (c[w:] - c[:-w]) / (sigma * np.sqrt(w))  # boxes starting at t = 0..nout-w
+            better = s > best[: nout - w + 1]
+            best[: nout - w + 1][better] = s[better]
+            bw[: nout - w + 1][better] = w
+        t = np.nonzero(best >= nsigma)[0]
+        ev = np.empty(len(t), dtype=EVENT_DTYPE)
+        ev["dm_row"] = d
+        ev["t"] = t
+        ev["width"] = bw[t]
+        ev["snr"] = best[t]
+        found.append(ev)
+    if not found:
+        return np.empty(0, dtype=EVENT_DTYPE)
+    ev = np.concatenate(found)
+    return ev[np.lexsort((ev["t"], ev["dm_row"]))]

@@ -853,7 +853,7 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
   if (in_t == DD_U8 && v == 3) {
     if (d == 8 && k == 8) return *out = make_impl<BodyCopies<uint8_t, 8, 2, 6>, uint8_t>(), true;
     if (d == 4 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 4, 4, 4>, uint8_t>(), true;
-    if (d == 8 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 8, 4, 2>, uint8_t>(), true;
+    if (d == 8 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 8, 4, 4>, uint8_t>(), true;
   }
   if (in_t == DD_U8 && v == 4) {
     if (d == 8 && k == 28)
