@@ -276,6 +276,43 @@ dd_status dd_serve_stats(dd_server* srv, int32_t* pending, int32_t* inflight, in
 
 dd_status dd_serve_destroy(dd_server* srv);
 
+/* ------------------------------------------------------------ detection
+ *
+ * The stage after de-dispersion (section 3, output thread; the boxcar S/N of
+ * Figure 5): every DM row is normalised by its own mean mu_d and population
+ * standard deviation sigma_d over its nout samples (FP64); for widths
+ * w = 1, 2, 4, ..., 2^max_log2_width the box starting at sample t has
+ * S/N (sum_{i<w} x[d][t+i] - w*mu_d) / (sigma_d*sqrt(w)), defined for
+ * t + w <= nout; sample (d, t) is an event when its best S/N over those
+ * widths is >= nsigma (the smallest width wins ties).  Rows with
+ * sigma_d = 0 have no events.
+ */
+typedef struct dd_event {
+  int32_t dm_row;   /* output row (the plan's DM index) */
+  int32_t width;    /* boxcar width in samples */
+  int64_t t;        /* first output sample of the box */
+  float snr;        /* S/N of that box (FP32) */
+  int32_t reserved; /* 0 */
+} dd_event;
+
+/*
+ * Detect events in a de-dispersed buffer d_out (ndms rows of out_stride
+ * elements; out_t DD_F32 or DD_I32; nout >= 1 samples per row used).
+ *   max_log2_width  0..6 (widths up to 64 samples)
+ *   d_stats         device, 2*ndms doubles, written: (mu_d, sigma_d) per row
+ *   d_events        device, room for max_events events (order unspecified)
+ *   d_count         device, one uint64, written: the number of events found,
+ *                   which may exceed max_events (only max_events of them are
+ *                   stored)
+ * All buffers belong to the caller; the work is queued on `stream` (NULL =
+ * default stream) and the results are valid once it completes.
+ * DD_ERR_INVALID_ARG for bad sizes or NULL pointers, DD_ERR_DTYPE for other
+ * output types.
+ */
+dd_status dd_detect(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nout,
+                    int64_t out_stride, float nsigma, int32_t max_log2_width, double* d_stats,
+                    dd_event* d_events, int64_t max_events, uint64_t* d_count, void* stream);
+
 /* ------------------------------------------------------------------------ */
 
 const char* dd_status_str(dd_status s);

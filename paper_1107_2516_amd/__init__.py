@@ -108,6 +108,7 @@ _SIGS = {
     "dd_serve_destroy": [_P],
     "dd_serve_stats": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                        ctypes.POINTER(ctypes.c_size_t)],
+    "dd_detect": [_P, ctypes.c_int, _I32, _I64, _I64, ctypes.c_float, _I32, _P, _P, _I64, _P, _P],
 }
 
 
@@ -442,3 +443,34 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# dd_event as a numpy record (24 bytes, the C layout)
+EVENT_DTYPE = np.dtype([("dm_row", np.int32), ("width", np.int32), ("t", np.int64),
+                        ("snr", np.float32), ("reserved", np.int32)])
+
+
+def detect(out, nsigma, max_log2_width=6, max_events=1 << 20, stream=None):
+    """Detection stage on a de-dispersed tensor out [ndms, nout] (float32 or
+    int32, rows contiguous): per-row mean/sigma, boxcars of widths 1..2^k,
+    events where a sample's best S/N >= nsigma.  Returns (events sorted by
+    (dm_row, t) as a numpy record array, per-row stats tensor [ndms, 2]
+    (mu, sigma), total number of events found)."""
+    torch = _torch()
+    if out.dim() != 2 or out.stride(1) != 1:
+        raise DedispError(DD_ERR_INVALID_ARG, "out must be [ndms, nout] with contiguous rows")
+    ndms, nout = out.shape
+    stats = torch.empty((ndms, 2), dtype=torch.float64, device=out.device)
+    ev = torch.empty((max(1, max_events), EVENT_DTYPE.itemsize), dtype=torch.uint8,
+                     device=out.device)
+    count = torch.zeros(1, dtype=torch.int64, device=out.device)
+    _check(lib().dd_detect(out.data_ptr(), dtype_code(out.dtype), ndms, nout, out.stride(0),
+                           float(nsigma), int(max_log2_width), stats.data_ptr(), ev.data_ptr(),
+                           int(max_events), count.data_ptr(), stream_handle(stream)))
+    s = torch.cuda.current_stream() if stream is None else stream
+    s.synchronize()
+    n = int(count.item())
+    k = min(n, max_events)
+    host = ev[:k].cpu().numpy().reshape(-1).view(EVENT_DTYPE)
+    host = host[np.lexsort((host["t"], host["dm_row"]))]
+    return host, stats, n

@@ -1,0 +1,174 @@
+// Detection after de-dispersion (section 3, output thread; the boxcar S/N
+// of Figure 5): per-row mean and standard deviation, boxcar sums of widths
+// 1, 2, 4, ..., 64, and an n-sigma threshold on each sample's best width.
+//
+// Two passes over the de-dispersed buffer, both HBM-bound:
+//  1. k_row_stats: one workgroup per DM row accumulates sum and sum of
+//     squares of (x - x[0]) in FP64 (the shift keeps the squares small) and
+//     writes (mu, sigma).
+//  2. k_boxcar: a workgroup owns 4096 consecutive samples of one row; it
+//     stages y = x - mu (FP32) plus a 64-sample halo in LDS (one padding
+//     word every 16 so that a lane's 16-sample run starts in its own bank
+//     group), and each lane turns its 16 samples + halo into register prefix
+//     sums, from which every box of every width is one subtraction.  Events
+//     are appended with one 64-bit atomic per event.
+#include "dd_internal.h"
+
+namespace dd {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRun = 16;                  // samples per lane
+constexpr int kTile = kThreads * kRun;    // samples per workgroup
+constexpr int kHalo = 64;                 // the widest box
+constexpr int kStage = kTile + kHalo;     // staged samples
+constexpr int kLds = kStage + kStage / 16 + 1;
+
+__device__ __forceinline__ int padded(int i) { return i + (i >> 4); }
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_row_stats(const T* __restrict__ in, int64_t stride,
+                                                        int64_t nout, double* __restrict__ stats) {
+  const int d = blockIdx.x;
+  const T* row = in + static_cast<int64_t>(d) * stride;
+  const double k0 = static_cast<double>(row[0]);
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t t = threadIdx.x; t < nout; t += kThreads) {
+    const double v = static_cast<double>(row[t]) - k0;
+    s1 += v;
+    s2 = fma(v, v, s2);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+  }
+  __shared__ double r1[kThreads / 64], r2[kThreads / 64];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    r1[wave] = s1;
+    r2[wave] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < kThreads / 64; w++) {
+      a += r1[w];
+      b += r2[w];
+    }
+    const double n = static_cast<double>(nout);
+    const double m = a / n;
+    const double var = b / n - m * m;
+    stats[2 * d] = k0 + m;
+    stats[2 * d + 1] = var > 0.0 ? sqrt(var) : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, int64_t stride,
+                                                     int64_t nout, const double* __restrict__ stats,
+                                                     float nsigma, int kmax,
+                                                     dd_event* __restrict__ events,
+                                                     int64_t max_events,
+                                                     unsigned long long* __restrict__ count) {
+  __shared__ float y[kLds];
+  const int d = blockIdx.y;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTile;
+  const double mu = stats[2 * d];
+  const double sg = stats[2 * d + 1];
+  if (!(sg > 0.0)) return;  // the whole workgroup: no events in a flat row
+  const T* row = in + static_cast<int64_t>(d) * stride;
+  for (int i = threadIdx.x; i < kStage; i += kThreads) {
+    const int64_t t = t0 + i;
+    y[padded(i)] = t < nout ? static_cast<float>(static_cast<double>(row[t]) - mu) : 0.f;
+  }
+  __syncthreads();
+  const int base = threadIdx.x * kRun;
+  float p[kRun + kHalo];  // p[j] = sum of the lane's first j staged samples
+  float acc = 0.f;
+  p[0] = 0.f;
+#pragma unroll
+  for (int j = 1; j < kRun + kHalo; j++) {
+    acc += y[padded(base + j - 1)];
+    p[j] = acc;
+  }
+  float inv[7];
+#pragma unroll
+  for (int k = 0; k < 7; k++) inv[k] = static_cast<float>(1.0 / (sg * sqrt(static_cast<double>(1 << k))));
+#pragma unroll
+  for (int i = 0; i < kRun; i++) {
+    const int64_t t = t0 + base + i;
+    if (t >= nout) break;
+    float best = -INFINITY;
+    int bw = 0;
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+      const int w = 1 << k;
+      if (k <= kmax && t + w <= nout) {
+        const float s = (p[i + w] - p[i]) * inv[k];
+        if (s > best) {
+          best = s;
+          bw = w;
+        }
+      }
+    }
+    if (best >= nsigma) {
+      const unsigned long long at = atomicAdd(count, 1ull);
+      if (at < static_cast<unsigned long long>(max_events)) {
+        dd_event e;
+        e.dm_row = d;
+        e.width = bw;
+        e.t = t;
+        e.snr = best;
+        e.reserved = 0;
+        events[at] = e;
+      }
+    }
+  }
+}
+
+__global__ void k_clear_count(unsigned long long* count) { *count = 0ull; }
+
+template <typename T>
+dd_status launch_detect(const T* in, int32_t ndms, int64_t nout, int64_t stride, float nsigma,
+                        int kmax, double* stats, dd_event* events, int64_t max_events,
+                        unsigned long long* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(1), 0, st, count);
+  DD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_row_stats<T>, dim3(ndms), dim3(kThreads), 0, st, in, stride, nout, stats);
+  DD_HIP(hipGetLastError());
+  const int64_t ntiles = (nout + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_boxcar<T>, dim3(static_cast<unsigned>(ntiles), ndms), dim3(kThreads), 0, st,
+                     in, stride, nout, stats, nsigma, kmax, events, max_events, count);
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+}  // namespace
+}  // namespace dd
+
+extern "C" dd_status dd_detect(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nout,
+                               int64_t out_stride, float nsigma, int32_t max_log2_width,
+                               double* d_stats, dd_event* d_events, int64_t max_events,
+                               uint64_t* d_count, void* stream) {
+  try {
+    if (!d_out || !d_stats || !d_count || (max_events > 0 && !d_events))
+      return dd::set_error(DD_ERR_INVALID_ARG, "NULL buffer");
+    if (ndms < 1 || ndms > 65535 || nout < 1 || out_stride < nout || max_events < 0)
+      return dd::set_error(DD_ERR_INVALID_ARG, "bad sizes");
+    if (nout > (int64_t(1) << 40)) return dd::set_error(DD_ERR_TOO_LARGE, "rows too long");
+    if (max_log2_width < 0 || max_log2_width > 6)
+      return dd::set_error(DD_ERR_INVALID_ARG, "max_log2_width must be 0..6");
+    if (!(nsigma == nsigma)) return dd::set_error(DD_ERR_INVALID_ARG, "nsigma is NaN");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto* cnt = reinterpret_cast<unsigned long long*>(d_count);
+    if (out_t == DD_F32)
+      return dd::launch_detect(static_cast<const float*>(d_out), ndms, nout, out_stride, nsigma,
+                               max_log2_width, d_stats, d_events, max_events, cnt, st);
+    if (out_t == DD_I32)
+      return dd::launch_detect(static_cast<const int32_t*>(d_out), ndms, nout, out_stride, nsigma,
+                               max_log2_width, d_stats, d_events, max_events, cnt, st);
+    return dd::set_error(DD_ERR_DTYPE, "detection reads f32 or int32 rows");
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
+}

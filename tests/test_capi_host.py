@@ -104,3 +104,26 @@ def test_execute_argument_errors_before_any_gpu_work():
     assert L.dd_execute(p.handle, fake, dd.DD_U8, 100000, 100000, fake, dd.DD_F32, 100000, None) == dd.DD_ERR_DTYPE
     assert L.dd_execute(p.handle, fake, dd.DD_F32, p.max_shift, p.max_shift, fake, dd.DD_F32, 1, None) == dd.DD_ERR_NSAMP
     assert L.dd_execute(p.handle, fake, dd.DD_F32, 1000, 999, fake, dd.DD_F32, 1000, None) == dd.DD_ERR_INVALID_ARG
+
+
+def test_detect_argument_errors_before_any_gpu_work():
+    """dd_detect validates sizes, widths and types before it queues work."""
+    L = dd.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the call fails first
+    ok = dict(out_t=dd.DD_F32, ndms=4, nout=100, stride=100, nsigma=5.0, kmax=6, max_events=10)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.dd_detect(fake, a["out_t"], a["ndms"], a["nout"], a["stride"], a["nsigma"],
+                           a["kmax"], fake, fake, a["max_events"], fake, None)
+
+    assert L.dd_detect(None, dd.DD_F32, 4, 100, 100, 5.0, 6, fake, fake, 10, fake, None) == dd.DD_ERR_INVALID_ARG
+    assert call(kmax=7) == dd.DD_ERR_INVALID_ARG
+    assert call(kmax=-1) == dd.DD_ERR_INVALID_ARG
+    assert call(nout=0) == dd.DD_ERR_INVALID_ARG
+    assert call(stride=99) == dd.DD_ERR_INVALID_ARG
+    assert call(ndms=0) == dd.DD_ERR_INVALID_ARG
+    assert call(max_events=-1) == dd.DD_ERR_INVALID_ARG
+    assert call(nsigma=float("nan")) == dd.DD_ERR_INVALID_ARG
+    assert call(out_t=dd.DD_U8) == dd.DD_ERR_DTYPE
+    assert call(out_t=dd.DD_F16) == dd.DD_ERR_DTYPE
