@@ -65,6 +65,8 @@ def parse():
                              "serve_u8"])
     ap.add_argument("--only", action="store_true",
                     help="time only the named workload (no precision/batch/serve blocks)")
+    ap.add_argument("--detect", action="store_true",
+                    help="with --only: also time the detection stage on the FP32 output")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample")
@@ -653,6 +655,7 @@ def main():
                          "pulse_snr": pulse_snrs(o, w, pulses)}
         prec["injected_snr"] = [p["snr"] for p in pulses]
         line["precision"] = prec
+    if (extras or args.detect) and dt == "f32":
         log("detect: timing")
         line["detect"] = run_detect(dd, torch, main_out, w, pulses, args)
     if not args.no_cpu_baseline:

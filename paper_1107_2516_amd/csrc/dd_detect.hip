@@ -7,11 +7,11 @@
 //     squares of (x - x[0]) in FP64 (the shift keeps the squares small) and
 //     writes (mu, sigma).
 //  2. k_boxcar: a workgroup owns 4096 consecutive samples of one row; it
-//     stages y = x - mu (FP32) plus a 64-sample halo in LDS (one padding
-//     word every 16 so that a lane's 16-sample run starts in its own bank
-//     group), and each lane turns its 16 samples + halo into register prefix
+//     stages y = x - mu (FP32) plus a 64-sample halo in LDS (four padding
+//     words every 16 so that lanes read their runs with conflict-free 16-byte
+//     reads), and each lane turns its 16 samples + halo into register prefix
 //     sums, from which every box of every width is one subtraction.  Events
-//     are appended with one 64-bit atomic per event.
+//     are appended with one 64-bit atomic per wavefront and sample slot.
 #include "dd_internal.h"
 
 namespace dd {
@@ -22,9 +22,12 @@ constexpr int kRun = 16;                  // samples per lane
 constexpr int kTile = kThreads * kRun;    // samples per workgroup
 constexpr int kHalo = 64;                 // the widest box
 constexpr int kStage = kTile + kHalo;     // staged samples
-constexpr int kLds = kStage + kStage / 16 + 1;
+constexpr int kLds = kStage + (kStage / 16) * 4 + 4;
 
-__device__ __forceinline__ int padded(int i) { return i + (i >> 4); }
+// LDS position of staged sample i: four padding words after every 16, so a
+// lane's run of 16 starts 80 bytes after its neighbour's and 16-byte reads of
+// 8 consecutive lanes fall in distinct bank groups
+__device__ __forceinline__ int padded(int i) { return i + ((i >> 4) << 2); }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row_stats(const T* __restrict__ in, int64_t stride,
@@ -33,10 +36,23 @@ __global__ __launch_bounds__(kThreads) void k_row_stats(const T* __restrict__ in
   const T* row = in + static_cast<int64_t>(d) * stride;
   const double k0 = static_cast<double>(row[0]);
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t t = threadIdx.x; t < nout; t += kThreads) {
-    const double v = static_cast<double>(row[t]) - k0;
-    s1 += v;
-    s2 = fma(v, v, s2);
+  constexpr int U = 8;  // loads in flight per lane
+  int64_t t = threadIdx.x;
+  for (; t + (U - 1) * kThreads < nout; t += U * kThreads) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = row[t + u * kThreads];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const double a = static_cast<double>(v[u]) - k0;
+      s1 += a;
+      s2 = fma(a, a, s2);
+    }
+  }
+  for (; t < nout; t += kThreads) {
+    const double a = static_cast<double>(row[t]) - k0;
+    s1 += a;
+    s2 = fma(a, a, s2);
   }
   for (int o = 32; o > 0; o >>= 1) {
     s1 += __shfl_xor(s1, o);
@@ -70,16 +86,31 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
                                                      dd_event* __restrict__ events,
                                                      int64_t max_events,
                                                      unsigned long long* __restrict__ count) {
-  __shared__ float y[kLds];
+  __shared__ __align__(16) float y[kLds];
   const int d = blockIdx.y;
   const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTile;
   const double mu = stats[2 * d];
   const double sg = stats[2 * d + 1];
   if (!(sg > 0.0)) return;  // the whole workgroup: no events in a flat row
   const T* row = in + static_cast<int64_t>(d) * stride;
-  for (int i = threadIdx.x; i < kStage; i += kThreads) {
-    const int64_t t = t0 + i;
-    y[padded(i)] = t < nout ? static_cast<float>(static_cast<double>(row[t]) - mu) : 0.f;
+  constexpr int NL = (kStage + kThreads - 1) / kThreads;  // loads per lane
+  if (t0 + kStage <= nout) {  // whole tile inside the row: all loads in flight at once
+    T v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int i = threadIdx.x + u * kThreads;
+      v[u] = i < kStage ? row[t0 + i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int i = threadIdx.x + u * kThreads;
+      if (i < kStage) y[padded(i)] = static_cast<float>(static_cast<double>(v[u]) - mu);
+    }
+  } else {
+    for (int i = threadIdx.x; i < kStage; i += kThreads) {
+      const int64_t t = t0 + i;
+      y[padded(i)] = t < nout ? static_cast<float>(static_cast<double>(row[t]) - mu) : 0.f;
+    }
   }
   __syncthreads();
   const int base = threadIdx.x * kRun;
@@ -87,40 +118,70 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
   float acc = 0.f;
   p[0] = 0.f;
 #pragma unroll
-  for (int j = 1; j < kRun + kHalo; j++) {
-    acc += y[padded(base + j - 1)];
-    p[j] = acc;
+  for (int c = 0; c < (kRun + kHalo) / 16; c++) {  // the run and its halo, 16 samples at a time
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const float4 f = *reinterpret_cast<const float4*>(&y[padded(base + 16 * c) + 4 * q]);
+      v[4 * q] = f.x;
+      v[4 * q + 1] = f.y;
+      v[4 * q + 2] = f.z;
+      v[4 * q + 3] = f.w;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const int k = 16 * c + j + 1;
+      if (k < kRun + kHalo) {
+        acc += v[j];
+        p[k] = acc;
+      }
+    }
   }
   float inv[7];
 #pragma unroll
   for (int k = 0; k < 7; k++) inv[k] = static_cast<float>(1.0 / (sg * sqrt(static_cast<double>(1 << k))));
+  // every box of the tile ends inside the row: no per-box range test
+  const bool inside = t0 + kTile + kHalo <= nout;
 #pragma unroll
   for (int i = 0; i < kRun; i++) {
     const int64_t t = t0 + base + i;
-    if (t >= nout) break;
-    float best = -INFINITY;
-    int bw = 0;
+    float m = -INFINITY;  // the best S/N of the sample (max over widths)
+    if (inside) {
 #pragma unroll
-    for (int k = 0; k < 7; k++) {
-      const int w = 1 << k;
-      if (k <= kmax && t + w <= nout) {
-        const float s = (p[i + w] - p[i]) * inv[k];
-        if (s > best) {
-          best = s;
-          bw = w;
-        }
-      }
+      for (int k = 0; k < 7; k++)
+        if (k <= kmax) m = fmaxf(m, (p[i + (1 << k)] - p[i]) * inv[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 7; k++)
+        if (k <= kmax && t + (1 << k) <= nout) m = fmaxf(m, (p[i + (1 << k)] - p[i]) * inv[k]);
     }
-    if (best >= nsigma) {
-      const unsigned long long at = atomicAdd(count, 1ull);
-      if (at < static_cast<unsigned long long>(max_events)) {
-        dd_event e;
-        e.dm_row = d;
-        e.width = bw;
-        e.t = t;
-        e.snr = best;
-        e.reserved = 0;
-        events[at] = e;
+    const bool hit = m >= nsigma;
+    float best = m;
+    int bw = 0;
+    if (hit) {  // rare: the smallest width that reaches the maximum
+#pragma unroll
+      for (int k = 6; k >= 0; k--)
+        if (k <= kmax && t + (1 << k) <= nout && (p[i + (1 << k)] - p[i]) * inv[k] == m) bw = 1 << k;
+    }
+    // one atomic per wavefront: the lanes with an event take consecutive slots
+    const unsigned long long mask = __ballot(hit);
+    if (mask) {
+      const int lane = threadIdx.x & 63;
+      const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+      unsigned long long first = 0;
+      if (lane == leader) first = atomicAdd(count, static_cast<unsigned long long>(__popcll(mask)));
+      first = __shfl(first, leader);
+      if (hit) {
+        const unsigned long long at = first + __popcll(mask & ((1ull << lane) - 1ull));
+        if (at < static_cast<unsigned long long>(max_events)) {
+          dd_event e;
+          e.dm_row = d;
+          e.width = bw;
+          e.t = t;
+          e.snr = best;
+          e.reserved = 0;
+          events[at] = e;
+        }
       }
     }
   }
