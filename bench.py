@@ -24,8 +24,9 @@ Workloads (synthetic, seeded; see synth/):
 
 By default (scale_f32) the line also carries "precision" (u8 and f16 on the
 same data, with their error and the S/N of the injected pulses), "detect"
-(the detection stage on the FP32 output), "batch" and "serve" blocks; --only
-drops them.
+(the detection stage on the FP32 output), "corner_turn" (time-ordered
+spectra to channel order for the FP32 input), "batch" and "serve" blocks;
+--only drops them.
 """
 import argparse
 import json
@@ -67,6 +68,8 @@ def parse():
                     help="time only the named workload (no precision/batch/serve blocks)")
     ap.add_argument("--detect", action="store_true",
                     help="with --only: also time the detection stage on the FP32 output")
+    ap.add_argument("--corner", action="store_true",
+                    help="with --only: also time the corner turn of the FP32 input")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample")
@@ -328,6 +331,29 @@ def run_detect(dd, torch, out, w, pulses, args, nsigma=8.0, kmax=6):
                          "unit": "GB/s", "frac": achieved / PEAK_HBM_BPS,
                          "alg_bytes_per_launch": alg,
                          "note": "algorithmic bytes = one read of the output; the stage reads it twice"}}
+
+
+# --------------------------------------------------------------------------
+# Corner turn (time-ordered spectra -> the path's channel order)
+
+
+def run_corner(dd, torch, x32, args):
+    """dd_corner_turn of the FP32 workload's input from spectra [nsamp,
+    nchans] (as a telescope writes them) to rows [nchans, nsamp]."""
+    dev = torch.device("cuda:0")
+    spectra = torch.from_numpy(np.ascontiguousarray(x32.T)).to(dev)
+    out = torch.empty((x32.shape[0], x32.shape[1]), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    kms, wall_ms = timed(stream, lambda: dd.corner_turn(spectra, out=out), args.steps, args.warmup)
+    ok = bool(torch.equal(out[:, :4096].cpu(), torch.from_numpy(x32[:, :4096])))
+    nbytes = 2.0 * x32.size * 4
+    achieved = nbytes / (kms * 1e-3)
+    del spectra, out
+    return {"kernel_ms": kms, "ms_per_step": wall_ms, "shape": list(x32.shape[::-1]),
+            "matches_input_rows": ok,
+            "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM_BPS / 1e9,
+                         "unit": "GB/s", "frac": achieved / PEAK_HBM_BPS,
+                         "alg_bytes_per_launch": nbytes}}
 
 
 # --------------------------------------------------------------------------
@@ -658,6 +684,9 @@ def main():
     if (extras or args.detect) and dt == "f32":
         log("detect: timing")
         line["detect"] = run_detect(dd, torch, main_out, w, pulses, args)
+    if (extras or args.corner) and dt == "f32":
+        log("corner turn: timing")
+        line["corner_turn"] = run_corner(dd, torch, x32, args)
     if not args.no_cpu_baseline:
         if "f32" not in xs:
             xs["f32"] = x32

@@ -313,6 +313,23 @@ dd_status dd_detect(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nou
                     int64_t out_stride, float nsigma, int32_t max_log2_width, double* d_stats,
                     dd_event* d_events, int64_t max_events, uint64_t* d_count, void* stream);
 
+/* ------------------------------------------------------------ corner turn
+ *
+ * Telescope data arrive in time order (one spectrum of nchans channels per
+ * time sample); the path reads channel order (one time series per channel,
+ * section 3.1).  dd_corner_turn converts the first into the second:
+ *   out[c*out_stride + t] = in[t*in_stride + c']   (t < nsamp, c < nchans)
+ * with c' = c, or c' = nchans-1-c when flip != 0 (spectra stored with the
+ * lowest frequency first; the plan's channel 0 is the top of the band).
+ * d_in and d_out are device buffers of `type` (DD_U8, DD_F16 or DD_F32)
+ * elements, in_stride >= nchans, out_stride >= nsamp; they must not overlap.
+ * Queued on `stream`.  DD_ERR_INVALID_ARG for bad sizes or NULL pointers,
+ * DD_ERR_DTYPE for other types.
+ */
+dd_status dd_corner_turn(const void* d_in, dd_dtype type, int64_t nsamp, int32_t nchans,
+                         int64_t in_stride, int32_t flip, void* d_out, int64_t out_stride,
+                         void* stream);
+
 /* ------------------------------------------------------------------------ */
 
 const char* dd_status_str(dd_status s);

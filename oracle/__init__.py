@@ -13,6 +13,9 @@ What it computes (paper section and equation cited at each function):
                     FP64 accumulation (f32/f16/f64 inputs) or int64 (u8).
 * `snr`, `detect`   buffer statistics and an n-sigma threshold emitting
                     (time, DM, intensity) triplets, section 3 (output thread).
+* `corner_turn`     time-ordered spectra -> channel-ordered time series
+                    (section 3.1's channel order), optionally reversing the
+                    channel axis.
 * `detect_boxcar`   the detection stage after the path: per-row mean and
                     standard deviation, boxcar sums of widths 1, 2, 4, ...,
                     an n-sigma threshold on the best width of each sample,
@@ -261,3 +264,13 @@ def detect_boxcar(out: np.ndarray, nsigma: float, max_log2_width: int, rows=None
         return np.empty(0, dtype=EVENT_DTYPE)
     ev = np.concatenate(found)
     return ev[np.lexsort((ev["t"], ev["dm_row"]))]
+
+
+def corner_turn(spectra: np.ndarray, flip: bool = False) -> np.ndarray:
+    """Section 3.1: the kernel reads each channel's time series contiguously
+    ("channel order"), telescope data come one spectrum per time sample.
+    out[c][t] = spectra[t][c] (or spectra[t][nchans-1-c] with flip)."""
+    x = np.asarray(spectra)
+    if flip:
+        x = x[:, ::-1]
+    return np.ascontiguousarray(x.T)

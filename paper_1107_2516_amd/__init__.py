@@ -109,6 +109,7 @@ _SIGS = {
     "dd_serve_stats": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                        ctypes.POINTER(ctypes.c_size_t)],
     "dd_detect": [_P, ctypes.c_int, _I32, _I64, _I64, ctypes.c_float, _I32, _P, _P, _I64, _P, _P],
+    "dd_corner_turn": [_P, ctypes.c_int, _I64, _I32, _I64, _I32, _P, _I64, _P],
 }
 
 
@@ -474,3 +475,21 @@ def detect(out, nsigma, max_log2_width=6, max_events=1 << 20, stream=None):
     host = ev[:k].cpu().numpy().reshape(-1).view(EVENT_DTYPE)
     host = host[np.lexsort((host["t"], host["dm_row"]))]
     return host, stats, n
+
+
+def corner_turn(spectra, flip=False, out=None, stream=None):
+    """Time-ordered spectra [nsamp, nchans] (uint8, float16 or float32 CUDA
+    tensor with contiguous rows) -> channel-ordered rows [nchans, nsamp]
+    (channels reversed when flip)."""
+    torch = _torch()
+    if spectra.dim() != 2 or spectra.stride(1) != 1:
+        raise DedispError(DD_ERR_INVALID_ARG, "spectra must be [nsamp, nchans] with contiguous rows")
+    nsamp, nchans = spectra.shape
+    if out is None:
+        out = torch.empty((nchans, nsamp), dtype=spectra.dtype, device=spectra.device)
+    if out.dim() != 2 or out.stride(1) != 1 or tuple(out.shape) != (nchans, nsamp):
+        raise DedispError(DD_ERR_INVALID_ARG, "out must be [nchans, nsamp] with contiguous rows")
+    _check(lib().dd_corner_turn(spectra.data_ptr(), dtype_code(spectra.dtype), nsamp, nchans,
+                                spectra.stride(0), 1 if flip else 0, out.data_ptr(), out.stride(0),
+                                stream_handle(stream)))
+    return out

@@ -127,3 +127,14 @@ def test_detect_argument_errors_before_any_gpu_work():
     assert call(nsigma=float("nan")) == dd.DD_ERR_INVALID_ARG
     assert call(out_t=dd.DD_U8) == dd.DD_ERR_DTYPE
     assert call(out_t=dd.DD_F16) == dd.DD_ERR_DTYPE
+
+
+def test_corner_turn_argument_errors_before_any_gpu_work():
+    L = dd.lib()
+    a = ctypes.c_void_p(0x1000)
+    b = ctypes.c_void_p(0x100000)
+    assert L.dd_corner_turn(None, dd.DD_U8, 10, 4, 4, 0, b, 10, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_corner_turn(a, dd.DD_U8, 10, 4, 3, 0, b, 10, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_corner_turn(a, dd.DD_U8, 10, 4, 4, 0, b, 9, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_corner_turn(a, dd.DD_I32, 10, 4, 4, 0, b, 10, None) == dd.DD_ERR_DTYPE
+    assert L.dd_corner_turn(a, dd.DD_F32, 10, 4, 4, 0, ctypes.c_void_p(0x1010), 10, None) == dd.DD_ERR_INVALID_ARG
