@@ -13,6 +13,9 @@ What it computes (paper section and equation cited at each function):
                     FP64 accumulation (f32/f16/f64 inputs) or int64 (u8).
 * `snr`, `detect`   buffer statistics and an n-sigma threshold emitting
                     (time, DM, intensity) triplets, section 3 (output thread).
+* `subband_dedisperse`  section 3.2's approximate method: binning, subband
+                    de-dispersion at nominal DMs, then brute force over the
+                    subbands for the fine DMs of each nominal DM.
 * `corner_turn`     time-ordered spectra -> channel-ordered time series
                     (section 3.1's channel order), optionally reversing the
                     channel axis.
@@ -29,6 +32,7 @@ the paper or the mathematics fix (exact rationals, closed forms, special
 cases, invariants, the paper's worked example).  None is "parity unpinned".
 """
 import ctypes
+import math
 import os
 import threading
 
@@ -274,3 +278,66 @@ def corner_turn(spectra: np.ndarray, flip: bool = False) -> np.ndarray:
     if flip:
         x = x[:, ::-1]
     return np.ascontiguousarray(x.T)
+
+
+def bin_samples(data: np.ndarray, b: int) -> np.ndarray:
+    """Section 3.2 binning: the mean of b adjacent samples,
+    out[c][t] = (1/b) * sum_{j<b} in[c][t*b + j], t < floor(nsamp/b)."""
+    x = np.asarray(data, dtype=np.float64)
+    n = x.shape[1] // b
+    return x[:, : n * b].reshape(x.shape[0], n, b).sum(axis=2) / b
+
+
+def subband_pass_dms(dm_lo: float, dm_hi: float, ddm: float, dsub: float):
+    """The fine DMs of one pass (dm_lo + i*ddm < dm_hi), the nominal DMs
+    (centres of the sub-ranges of width dsub that split [dm_lo, dm_hi)) and
+    each fine DM's nominal index."""
+    nfine = int(math.ceil((dm_hi - dm_lo) / ddm - 1e-9))
+    nnom = int(math.ceil((dm_hi - dm_lo) / dsub - 1e-9))
+    fine = dm_lo + np.arange(nfine, dtype=np.float64) * ddm
+    nominal = dm_lo + (np.arange(nnom, dtype=np.float64) + 0.5) * dsub
+    k = np.minimum(nnom - 1, np.floor((fine - dm_lo) / dsub).astype(np.int64))
+    return fine, nominal, k
+
+
+def subband_dedisperse(data: np.ndarray, nchans: int, f_top: float, df: float, t_samp: float,
+                       nsub: int, passes):
+    """Section 3.2 subband de-dispersion, one pass per (dm_lo, dm_hi, ddm,
+    dsub, bin) entry of a survey plan (Table 1).  For a pass with binning b
+    (sampling time t_samp*b, delays from the same law at that resolution):
+
+    * the channels are binned (bin_samples);
+    * channel c belongs to subband s = c // ceil(nchans/nsub), whose top
+      channel is c_s; for every nominal DM D_k the subband is de-dispersed
+      with shifts delay(D_k, c) - delay(D_k, c_s) into one series sub[s][k];
+    * each fine DM d of nominal k is the brute-force sum over subbands of
+      sub[s][k] shifted by delay(d, c_s).
+
+    Every sub[s][k] is cut to the pass's common length nsamp_b - M1 (M1 the
+    largest stage-1 shift) and every fine row to nsamp_b - M1 - M2 (M2 the
+    largest stage-2 shift).  Returns a list with one [nfine, nout] array per
+    pass (FP64)."""
+    x = np.asarray(data, dtype=np.float64)
+    cps = -(-nchans // nsub)
+    tops = np.arange(0, nchans, cps)
+    result = []
+    for (dm_lo, dm_hi, ddm, dsub, b) in passes:
+        xb = bin_samples(x, int(b)) if b > 1 else x
+        ts = t_samp * b
+        fine, nominal, k_of = subband_pass_dms(dm_lo, dm_hi, ddm, dsub)
+        dn = delay_table(nchans, f_top, df, ts, nominal)  # [nnom, nchans]
+        m1 = max(int((dn[:, c0:c0 + cps] - dn[:, [c0]]).max()) for c0 in tops)
+        n1 = xb.shape[1] - m1
+        sub = np.zeros((len(tops), len(nominal), n1))
+        for s, c0 in enumerate(tops):
+            t1 = dn[:, c0:c0 + cps] - dn[:, [c0]]
+            sub[s] = dedisperse(xb[c0:c0 + cps], t1, t_end=n1) if n1 > 0 else 0.0
+        df_tab = delay_table(nchans, f_top, df, ts, fine)[:, tops]  # [nfine, nsub]
+        m2 = int(df_tab.max())
+        n2 = n1 - m2
+        out = np.zeros((len(fine), max(n2, 0)))
+        for i in range(len(fine)):
+            rows = sub[:, k_of[i], :]  # [nsub, n1]
+            out[i] = dedisperse(rows, df_tab[[i]], t_end=n2)[0] if n2 > 0 else 0.0
+        result.append(out)
+    return result
