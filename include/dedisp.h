@@ -313,6 +313,57 @@ dd_status dd_detect(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nou
                     int64_t out_stride, float nsigma, int32_t max_log2_width, double* d_stats,
                     dd_event* d_events, int64_t max_events, uint64_t* d_count, void* stream);
 
+/* ------------------------------------------------------------ subband
+ *
+ * Section 3.2's approximate method for large DM ranges, as a survey plan of
+ * passes (Table 1).  For a pass {dm_lo, dm_hi, ddm, dsub, bin}:
+ *   fine DMs     dm_lo + i*ddm < dm_hi (the output rows of the pass)
+ *   nominal DMs  dm_lo + (k + 0.5)*dsub, the centres of the sub-ranges of
+ *                width dsub; fine DM d belongs to k = floor((d - dm_lo)/dsub)
+ *   binning      the mean of `bin` adjacent samples; shifts of the pass use
+ *                the delay law at t_samp*bin
+ *   stage 1      channel c is in subband s = c / ceil(nchans/nsub) with top
+ *                channel c_s; sub[s][k][t] = sum over its channels of
+ *                binned[c][t + delay(D_k, c) - delay(D_k, c_s)]
+ *   stage 2      out[d][t] = sum over s of sub[s][k(d)][t + delay(d, c_s)]
+ * Stage-1 series are cut to nsamp_b - M1 samples (M1 the pass's largest
+ * stage-1 shift, nsamp_b = nsamp / bin) and the pass's rows to
+ * nsamp_b - M1 - M2 (M2 its largest stage-2 shift).  FP32 input and output;
+ * both stages run the brute-force kernels.
+ */
+typedef struct dd_subband_plan dd_subband_plan;
+typedef struct dd_subband_pass {
+  double dm_lo, dm_hi; /* DM range [dm_lo, dm_hi) */
+  double ddm;          /* fine DM step */
+  double dsub;         /* nominal DM spacing */
+  int32_t bin;         /* binning factor >= 1 */
+  int32_t reserved;    /* 0 */
+} dd_subband_pass;
+
+/* nsub in 1..nchans; passes in increasing DM order.  DD_ERR_INVALID_ARG for
+ * bad bands, steps or pass lists. */
+dd_status dd_subband_plan_create(int32_t nchans, double f_top, double df, double t_samp,
+                                 int32_t nsub, const dd_subband_pass* passes, int32_t npass,
+                                 dd_subband_plan** out);
+/* Number of output rows (fine DMs over all passes) and passes. */
+dd_status dd_subband_plan_info(const dd_subband_plan* plan, int32_t* ndms, int32_t* npass);
+/* Host arrays of ndms entries: each row's DM and its pass index (either may
+ * be NULL). */
+dd_status dd_subband_dms(const dd_subband_plan* plan, double* dms, int32_t* pass_of_row);
+/* For nsamp input samples: each pass's output samples per row (npass
+ * entries, host) and the device workspace execute needs.  DD_ERR_NSAMP when
+ * some pass has no complete output sample. */
+dd_status dd_subband_sizes(const dd_subband_plan* plan, int64_t nsamp, int64_t* nout_per_pass,
+                           size_t* workspace_bytes);
+/* d_in [nchans][in_stride] FP32 (device), d_out [ndms][out_stride] FP32
+ * (device; row r holds nout of its pass, out_stride >= the largest), and a
+ * device workspace of at least the bytes dd_subband_sizes reported.  Queued
+ * on `stream`. */
+dd_status dd_subband_execute(const dd_subband_plan* plan, const float* d_in, int64_t nsamp,
+                             int64_t in_stride, float* d_out, int64_t out_stride, void* d_workspace,
+                             size_t workspace_bytes, void* stream);
+dd_status dd_subband_plan_destroy(dd_subband_plan* plan);
+
 /* ------------------------------------------------------------ corner turn
  *
  * Telescope data arrive in time order (one spectrum of nchans channels per

@@ -110,6 +110,12 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_size_t)],
     "dd_detect": [_P, ctypes.c_int, _I32, _I64, _I64, ctypes.c_float, _I32, _P, _P, _I64, _P, _P],
     "dd_corner_turn": [_P, ctypes.c_int, _I64, _I32, _I64, _I32, _P, _I64, _P],
+    "dd_subband_plan_create": [_I32, _D, _D, _D, _I32, _P, _I32, _PP],
+    "dd_subband_plan_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
+    "dd_subband_dms": [_P, _P, _P],
+    "dd_subband_sizes": [_P, _I64, _P, ctypes.POINTER(ctypes.c_size_t)],
+    "dd_subband_execute": [_P, _P, _I64, _I64, _P, _I64, _P, ctypes.c_size_t, _P],
+    "dd_subband_plan_destroy": [_P],
 }
 
 
@@ -493,3 +499,68 @@ def corner_turn(spectra, flip=False, out=None, stream=None):
                                 spectra.stride(0), 1 if flip else 0, out.data_ptr(), out.stride(0),
                                 stream_handle(stream)))
     return out
+
+
+class SubbandPass(ctypes.Structure):
+    _fields_ = [("dm_lo", ctypes.c_double), ("dm_hi", ctypes.c_double), ("ddm", ctypes.c_double),
+                ("dsub", ctypes.c_double), ("bin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SubbandPlan:
+    """Section 3.2 subband de-dispersion over a survey plan of passes
+    (dm_lo, dm_hi, ddm, dsub, bin), FP32 in and out."""
+
+    def __init__(self, nchans, f_top, df, t_samp, nsub, passes):
+        arr = (SubbandPass * len(passes))()
+        for i, (lo, hi, ddm, dsub, b) in enumerate(passes):
+            arr[i] = SubbandPass(float(lo), float(hi), float(ddm), float(dsub), int(b), 0)
+        h = ctypes.c_void_p()
+        _check(lib().dd_subband_plan_create(int(nchans), float(f_top), float(df), float(t_samp),
+                                            int(nsub), arr, len(passes), ctypes.byref(h)))
+        self._h = h
+        n, npass = _I32(), _I32()
+        _check(lib().dd_subband_plan_info(h, ctypes.byref(n), ctypes.byref(npass)))
+        self.ndms, self.npass = n.value, npass.value
+        self.nchans = int(nchans)
+
+    def dms(self):
+        d = np.zeros(self.ndms, dtype=np.float64)
+        p = np.zeros(self.ndms, dtype=np.int32)
+        _check(lib().dd_subband_dms(self._h, d.ctypes.data, p.ctypes.data))
+        return d, p
+
+    def sizes(self, nsamp):
+        n = np.zeros(self.npass, dtype=np.int64)
+        ws = ctypes.c_size_t()
+        _check(lib().dd_subband_sizes(self._h, int(nsamp), n.ctypes.data, ctypes.byref(ws)))
+        return n, ws.value
+
+    def execute(self, x, out=None, workspace=None, stream=None):
+        """x [nchans, nsamp] float32 CUDA tensor (contiguous rows).  Returns
+        (out [ndms, max nout], nout per pass); row r is valid up to the nout
+        of its pass."""
+        torch = _torch()
+        if x.dim() != 2 or x.stride(1) != 1 or x.shape[0] != self.nchans or x.dtype != torch.float32:
+            raise DedispError(DD_ERR_INVALID_ARG, "x must be float32 [nchans, nsamp]")
+        nsamp = x.shape[1]
+        nout, ws = self.sizes(nsamp)
+        if out is None:
+            out = torch.zeros((self.ndms, int(nout.max())), dtype=torch.float32, device=x.device)
+        if workspace is None:
+            workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device=x.device)
+        _check(lib().dd_subband_execute(self._h, x.data_ptr(), nsamp, x.stride(0), out.data_ptr(),
+                                        out.stride(0), workspace.data_ptr(),
+                                        workspace.numel(), stream_handle(stream)))
+        return out, nout
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_subband_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
