@@ -126,6 +126,8 @@ struct BatchLaunch {
 };
 dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
                         BatchLaunch* out);
+// Bytes of one beam's kernel parameters in a batch parameter array.
+size_t batch_param_size();
 // Zero the 8 work counters and launch the persistent kernel on `stream`.
 dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
                         unsigned* d_counters, hipStream_t stream);

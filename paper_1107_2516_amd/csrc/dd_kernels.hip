@@ -1032,6 +1032,8 @@ dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams
   return DD_OK;
 }
 
+size_t batch_param_size() { return sizeof(KParams); }
+
 dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
                         unsigned* d_counters, hipStream_t stream) {
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters, 8);

@@ -2,20 +2,20 @@
 // plan, bin the input, de-disperse every subband at the nominal DMs (stage
 // 1), then de-disperse the subband series at the fine DMs of each nominal DM
 // (stage 2).  Both stages are ordinary brute-force plans built from integer
-// shift tables and run by dd_execute; binning is a small HBM-bound kernel.
+// shift tables; each stage of a pass is one persistent multi-plan launch
+// (the batch kernel, one "beam" per subband or per nominal DM), so the many
+// small plans share one grid.  Binning is a small HBM-bound kernel.
 //
-// Device memory: the caller's workspace holds the binned input (passes with
-// bin > 1) followed by the stage-1 series [subband][nominal DM][n1]; passes
-// run one after another and reuse it.  A stage-2 launch reads channel s of
-// nominal k at sub + (s*nnom + k)*n1, i.e. channel stride nnom*n1.
+// Device memory, all in the caller's workspace: the binned input (passes
+// with bin > 1) and the stage-1 series [subband][nominal DM][n1], reused by
+// the passes in turn, then the parameter arrays of every stage launch
+// (uploaded once per call) and the work counters.  A stage-2 item reads
+// channel s of nominal k at sub + (s*nnom + k)*n1: channel stride nnom*n1.
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "dd_internal.h"
-
-extern "C" dd_status dd_execute(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
-                                int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
-                                void* stream);
 
 namespace dd {
 namespace {
@@ -61,13 +61,46 @@ namespace {
 
 int64_t pass_nb(const dd::Pass& ps, int64_t nsamp) { return nsamp / ps.p.bin; }
 
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
 size_t pass_workspace(const dd_subband_plan* sp, const dd::Pass& ps, int64_t nsamp) {
   const int64_t nb = pass_nb(ps, nsamp);
   const int64_t n1 = nb - ps.m1;
   size_t bytes = 0;
-  if (ps.p.bin > 1) bytes += ((static_cast<size_t>(sp->nchans) * nb * 4 + 255) / 256) * 256;
-  bytes += static_cast<size_t>(sp->nsub) * ps.nominal.size() * static_cast<size_t>(std::max<int64_t>(n1, 0)) * 4;
+  if (ps.p.bin > 1) bytes += round256(static_cast<size_t>(sp->nchans) * nb * 4);
+  bytes += round256(static_cast<size_t>(sp->nsub) * ps.nominal.size() *
+                    static_cast<size_t>(std::max<int64_t>(n1, 0)) * 4);
   return bytes;
+}
+
+int stage2_items(const dd::Pass& ps) {
+  int n = 0;
+  for (const dd_plan* q : ps.stage2) n += q != nullptr;
+  return n;
+}
+
+// parameter array + prefix sums of one stage launch with n items
+size_t param_area(int n) {
+  return round256(static_cast<size_t>(n) * dd::batch_param_size()) +
+         round256(static_cast<size_t>(n + 1) * 4);
+}
+
+size_t params_workspace(const dd_subband_plan* sp) {
+  size_t b = 256;  // the work counters
+  for (const dd::Pass& ps : sp->passes) b += param_area(sp->nsub) + param_area(stage2_items(ps));
+  return b;
+}
+
+// tile shape for a stage whose plans have at most `rows` DMs: the smallest
+// register-window DM tile that holds them
+dd::TileShape stage_shape(int rows) {
+  dd::TileShape s;
+  s.variant = 1;
+  s.waves = 4;
+  s.tsamp_per_lane = 12;
+  s.chans_per_stage = 8;
+  s.dms_per_wave = rows <= 16 ? 4 : (rows <= 24 ? 6 : 8);
+  return s;
 }
 
 }  // namespace
@@ -197,7 +230,7 @@ dd_status dd_subband_sizes(const dd_subband_plan* sp, int64_t nsamp, int64_t* no
     if (nout_per_pass) nout_per_pass[ip] = n;
     ws = std::max(ws, pass_workspace(sp, ps, nsamp));
   }
-  if (workspace_bytes) *workspace_bytes = ws;
+  if (workspace_bytes) *workspace_bytes = ws + params_workspace(sp);
   return DD_OK;
 }
 
@@ -216,38 +249,85 @@ dd_status dd_subband_execute(const dd_subband_plan* sp, const float* d_in, int64
     for (int64_t n : nout)
       if (out_stride < n) return dd::set_error(DD_ERR_INVALID_ARG, "out_stride too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t data_bytes = 0;
+    for (const dd::Pass& ps : sp->passes) data_bytes = std::max(data_bytes, pass_workspace(sp, ps, nsamp));
+    unsigned char* w0 = static_cast<unsigned char*>(d_workspace);
+    unsigned char* pbase = w0 + data_bytes;  // parameter arrays, then counters
+    // every stage launch of the call, prepared on the host
+    struct Stage {
+      dd::BatchLaunch bl;
+      size_t off = 0;  // parameter array offset from pbase; prefix sums follow
+    };
+    std::vector<Stage> stages;
+    std::vector<unsigned char> host(params_workspace(sp) - 256, 0);
+    size_t off = 0;
+    auto prepare = [&](std::vector<dd::ExecArgs>& items, int rows) -> dd_status {
+      Stage st;
+      const int n = static_cast<int>(items.size());
+      dd_status r = dd::batch_prepare(stage_shape(rows), DD_F32, items.data(), n, &st.bl);
+      if (r == DD_ERR_TOO_LARGE)  // shift spread beyond the window kernel's LDS: plain kernel
+        r = dd::batch_prepare(dd::default_shape(DD_F32, items[0].plan), DD_F32, items.data(), n, &st.bl);
+      if (r != DD_OK) return r;
+      st.off = off;
+      std::memcpy(host.data() + off, st.bl.params.data(), st.bl.params.size());
+      std::memcpy(host.data() + off + round256(st.bl.params.size()), st.bl.first_item.data(),
+                  st.bl.first_item.size() * 4);
+      off += param_area(n);
+      stages.push_back(std::move(st));
+      return DD_OK;
+    };
     for (size_t ip = 0; ip < sp->passes.size(); ip++) {
       const dd::Pass& ps = sp->passes[ip];
       const int64_t nb = pass_nb(ps, nsamp);
       const int64_t n1 = nb - ps.m1;
-      unsigned char* w = static_cast<unsigned char*>(d_workspace);
+      const int64_t nnom = static_cast<int64_t>(ps.nominal.size());
+      unsigned char* w = w0;
       const float* xb = d_in;
       int64_t xstride = in_stride;
       if (ps.p.bin > 1) {
-        float* binned = reinterpret_cast<float*>(w);
-        hipLaunchKernelGGL(dd::k_bin, dim3(static_cast<unsigned>((nb + 255) / 256), sp->nchans),
-                           dim3(256), 0, s, d_in, in_stride, ps.p.bin, nb, binned);
-        DD_HIP(hipGetLastError());
-        xb = binned;
+        xb = reinterpret_cast<const float*>(w);
         xstride = nb;
-        w += ((static_cast<size_t>(sp->nchans) * nb * 4 + 255) / 256) * 256;
+        w += round256(static_cast<size_t>(sp->nchans) * nb * 4);
       }
       float* sub = reinterpret_cast<float*>(w);
-      const int64_t nnom = static_cast<int64_t>(ps.nominal.size());
-      // stage 1: every subband at every nominal DM, n1 samples each
+      std::vector<dd::ExecArgs> it1, it2;
+      int rows1 = static_cast<int>(nnom), rows2 = 0;
       for (int su = 0; su < sp->nsub; su++) {
-        const dd_plan* q = ps.stage1[su];
-        st = dd_execute(q, xb + static_cast<int64_t>(su) * sp->cps * xstride, DD_F32,
-                        n1 + q->max_shift, xstride, sub + su * nnom * n1, DD_F32, n1, s);
-        if (st != DD_OK) return st;
+        dd_plan* q = ps.stage1[su];
+        it1.push_back(dd::ExecArgs{q, xb + static_cast<int64_t>(su) * sp->cps * xstride,
+                                   n1 + q->max_shift, xstride, sub + su * nnom * n1, n1, n1,
+                                   q->nchans});
       }
-      // stage 2: the fine DMs of each nominal DM, over the subbands
       for (int64_t k = 0; k < nnom; k++) {
-        const dd_plan* q = ps.stage2[k];
+        dd_plan* q = ps.stage2[k];
         if (!q) continue;
-        st = dd_execute(q, sub + k * n1, DD_F32, nout[ip] + q->max_shift, nnom * n1,
-                        d_out + static_cast<int64_t>(ps.row0 + ps.first_of_k[k]) * out_stride, DD_F32,
-                        out_stride, s);
+        rows2 = std::max(rows2, q->ndms);
+        it2.push_back(dd::ExecArgs{q, sub + k * n1, nout[ip] + q->max_shift, nnom * n1,
+                                   d_out + static_cast<int64_t>(ps.row0 + ps.first_of_k[k]) * out_stride,
+                                   out_stride, nout[ip], q->nchans});
+      }
+      st = prepare(it1, rows1);
+      if (st != DD_OK) return st;
+      st = prepare(it2, rows2);
+      if (st != DD_OK) return st;
+    }
+    DD_HIP(hipMemcpyAsync(pbase, host.data(), off, hipMemcpyHostToDevice, s));
+    unsigned* counters = reinterpret_cast<unsigned*>(pbase + host.size());
+    for (size_t ip = 0; ip < sp->passes.size(); ip++) {
+      const dd::Pass& ps = sp->passes[ip];
+      if (ps.p.bin > 1) {
+        const int64_t nb = pass_nb(ps, nsamp);
+        hipLaunchKernelGGL(dd::k_bin, dim3(static_cast<unsigned>((nb + 255) / 256), sp->nchans),
+                           dim3(256), 0, s, d_in, in_stride, ps.p.bin, nb,
+                           reinterpret_cast<float*>(w0));
+        DD_HIP(hipGetLastError());
+      }
+      for (int j = 0; j < 2; j++) {
+        const Stage& sg = stages[2 * ip + j];
+        st = dd::batch_enqueue(sg.bl, pbase + sg.off,
+                               reinterpret_cast<const int32_t*>(pbase + sg.off +
+                                                                round256(sg.bl.params.size())),
+                               counters, s);
         if (st != DD_OK) return st;
       }
     }
