@@ -16,6 +16,9 @@ What it computes (paper section and equation cited at each function):
 * `subband_dedisperse`  section 3.2's approximate method: binning, subband
                     de-dispersion at nominal DMs, then brute force over the
                     subbands for the fine DMs of each nominal DM.
+* `channelise_power` section 5's front end: an FFT of nfft consecutive
+                    complex voltages per coarse subband, the power of each
+                    bin, channel-ordered output.
 * `corner_turn`     time-ordered spectra -> channel-ordered time series
                     (section 3.1's channel order), optionally reversing the
                     channel axis.
@@ -341,3 +344,29 @@ def subband_dedisperse(data: np.ndarray, nchans: int, f_top: float, df: float, t
             out[i] = dedisperse(rows, df_tab[[i]], t_end=n2)[0] if n2 > 0 else 0.0
         result.append(out)
     return result
+
+
+def channel_bin(j: int, nfft: int) -> int:
+    """FFT bin carried by channel j of a subband: channels run from the
+    highest frequency down, bins k = nfft/2-1, ..., 1, 0, -1, ..., -nfft/2
+    (index mod nfft)."""
+    return (nfft // 2 - 1 - j) % nfft
+
+
+def channelise_power(volt: np.ndarray, nfft: int) -> np.ndarray:
+    """Section 5: channelisation (an FFT) and power of complex voltages.
+
+    volt [nsamp, nsub] complex, one spectrum of nsub coarse subbands per
+    time sample (subband 0 at the top of the band).  Output [nsub*nfft,
+    nsamp // nfft] float64: channel c = s*nfft + j holds |X_s,k(t)|^2 with
+    X_s,k(t) = sum_{n<nfft} volt[t*nfft + n, s] * exp(-2 pi i k n / nfft) and
+    k = channel_bin(j, nfft)."""
+    v = np.asarray(volt, dtype=np.complex128)
+    nsamp, nsub = v.shape
+    nt = nsamp // nfft
+    blocks = v[: nt * nfft].reshape(nt, nfft, nsub)
+    X = np.fft.fft(blocks, axis=1)  # [nt, nfft(k), nsub]
+    P = np.abs(X) ** 2
+    order = [channel_bin(j, nfft) for j in range(nfft)]
+    P = P[:, order, :]  # [nt, j, nsub]
+    return np.ascontiguousarray(P.transpose(2, 1, 0).reshape(nsub * nfft, nt))
