@@ -72,6 +72,8 @@ def parse():
                     help="with --only: also time the detection stage on the FP32 output")
     ap.add_argument("--corner", action="store_true",
                     help="with --only: also time the corner turn of the FP32 input")
+    ap.add_argument("--frontend", action="store_true",
+                    help="also run the section 5 front end (channelise + de-disperse) block")
     ap.add_argument("--subband", action="store_true",
                     help="with --only: also time subband de-dispersion (Table 1 plan)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -358,6 +360,84 @@ def run_corner(dd, torch, x32, args):
             "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM_BPS / 1e9,
                          "unit": "GB/s", "frac": achieved / PEAK_HBM_BPS,
                          "alg_bytes_per_launch": nbytes}}
+
+
+# --------------------------------------------------------------------------
+# Real-time front end (section 5) on the toy observation of its test
+
+
+def run_frontend(dd, torch, args, dm_row=333, t0=20000, width=8, amp=0.5):
+    """One buffer of the section 5 pipeline per step, as the paper times it:
+    copy 2^19 spectra of 256 complex subbands (12.8 us) from pinned host
+    memory, channelise (FFT of 8, power, channel order: 2048 channels at
+    102.4 us), de-disperse 500 DMs up to 60, copy the result back.  The sum
+    of the stages is compared with the buffer's duration (real time)."""
+    fe = synth.FrontEnd()
+    band = fe.band()
+    dms = fe.dms()
+    plan = dd.Plan(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    nt = fe.nspec // fe.nfft
+    nout = plan.nout(nt)
+    # a dispersed boxcar pulse, placed per subband and FFT bin of the front end
+    off = pulse_offsets(dd, band, float(dms[dm_row]))
+    start = np.empty((fe.nsub, fe.nfft), dtype=np.int64)
+    for j in range(fe.nfft):
+        start[:, (fe.nfft // 2 - 1 - j) % fe.nfft] = t0 + off[j::fe.nfft]
+    v = synth.voltages_with_pulse(fe.seed, nt, fe.nsub, fe.nfft, start, width, amp)
+    h_v = torch.empty((fe.nspec, fe.nsub), dtype=torch.complex64, pin_memory=True)
+    h_v.numpy()[:] = v
+    del v
+    dev = torch.device("cuda:0")
+    d_v = torch.empty_like(h_v, device=dev)
+    d_p = torch.empty((band.nchans, nt), dtype=torch.float32, device=dev)
+    d_out = torch.empty((plan.ndms, nout), dtype=torch.float32, device=dev)
+    h_out = torch.empty((plan.ndms, nout), dtype=torch.float32, pin_memory=True)
+    stream = torch.cuda.current_stream(dev)
+    tile = None
+    if not args.no_autotune:
+        d_v.copy_(h_v)
+        dd.channelise(d_v, fe.nfft, out=d_p)
+        tile, _ = plan.autotune(torch.float32, nt)
+    names = ["h2d", "channelise", "dedisperse", "d2h"]
+    acc = np.zeros(len(names))
+    steps = max(3, args.steps // 2)
+    for it in range(1 + steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ev[0].record(stream)
+        d_v.copy_(h_v, non_blocking=True)
+        ev[1].record(stream)
+        dd.channelise(d_v, fe.nfft, out=d_p)
+        ev[2].record(stream)
+        plan.execute(d_p, out=d_out)
+        ev[3].record(stream)
+        h_out.copy_(d_out, non_blocking=True)
+        ev[4].record(stream)
+        torch.cuda.synchronize()
+        if it:  # the first pass is warm-up
+            acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(len(names))]
+    ms = acc / steps
+    total = float(ms.sum())
+    buffer_ms = fe.nspec * fe.t_samp * 1e3
+    snr = boxcar_snr_peak(h_out[dm_row].numpy(), t0, width)
+    ch_bytes = fe.nspec * fe.nsub * 8.0 + band.nchans * nt * 4.0
+    ch_ach = ch_bytes / (ms[1] * 1e-3)
+    del d_v, d_p, d_out, h_v, h_out
+    torch.cuda.empty_cache()
+    return {"observation": "toy observation of the real-time test: 610 MHz centre, 20 MHz, "
+                           "256 subbands at 12.8 us, 8 channels per subband, 500 DMs to 60, "
+                           "buffers of 2^19 spectra (complex FP32 voltages)",
+            "stage_ms": {n: float(m) for n, m in zip(names, ms)}, "total_ms": total,
+            "buffer_ms": buffer_ms, "real_time_factor": total / buffer_ms,
+            "buffers_per_buffer_time": buffer_ms / total,
+            "paper_c1060_total_ms": 5785.0, "tile": tile,
+            "injected_pulse": {"dm": float(dms[dm_row]), "t0": t0, "width": width,
+                               "power_gain": 1.0 + amp,
+                               "expected_snr": amp * math.sqrt(band.nchans * width),
+                               "recovered_snr": snr},
+            "channelise_roofline": {"bound": "hbm", "achieved": ch_ach / 1e9,
+                                    "peak": PEAK_HBM_BPS / 1e9, "unit": "GB/s",
+                                    "frac": ch_ach / PEAK_HBM_BPS,
+                                    "alg_bytes_per_launch": ch_bytes}}
 
 
 # --------------------------------------------------------------------------
@@ -739,6 +819,9 @@ def main():
     if (extras or args.subband) and dt == "f32":
         log("subband: timing")
         line["subband"] = run_subband(dd, torch, w, x32, pulses, args)
+    if (extras or args.frontend) and dt == "f32":
+        log("front end: timing")
+        line["frontend"] = run_frontend(dd, torch, args)
     if not args.no_cpu_baseline:
         if "f32" not in xs:
             xs["f32"] = x32

@@ -364,6 +364,22 @@ dd_status dd_subband_execute(const dd_subband_plan* plan, const float* d_in, int
                              size_t workspace_bytes, void* stream);
 dd_status dd_subband_plan_destroy(dd_subband_plan* plan);
 
+/* ------------------------------------------------------------ front end
+ *
+ * Section 5's real-time front end: complex voltages of nsub coarse subbands
+ * (one spectrum per time sample, subband 0 at the top of the band) are
+ * channelised by an FFT of nfft consecutive samples per subband and turned
+ * into power, written directly in channel order:
+ *   out[(s*nfft + j)*out_stride + t] = |X_{s,k}(t)|^2,
+ *   X_{s,k}(t) = sum_{n<nfft} v[(t*nfft + n)*in_stride + s] exp(-2 pi i k n / nfft),
+ *   k = (nfft/2 - 1 - j) mod nfft   (channels run from high to low frequency)
+ * for t < nsamp / nfft.  v is interleaved complex FP32 (re, im), in_stride
+ * >= nsub complex elements between time samples; nfft in {2, 4, 8, 16};
+ * out_stride >= nsamp / nfft.  FP32 arithmetic.  Queued on `stream`.
+ */
+dd_status dd_channelise(const float* d_volt, int64_t nsamp, int32_t nsub, int64_t in_stride,
+                        int32_t nfft, float* d_out, int64_t out_stride, void* stream);
+
 /* ------------------------------------------------------------ corner turn
  *
  * Telescope data arrive in time order (one spectrum of nchans channels per

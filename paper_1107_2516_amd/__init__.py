@@ -110,6 +110,7 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_size_t)],
     "dd_detect": [_P, ctypes.c_int, _I32, _I64, _I64, ctypes.c_float, _I32, _P, _P, _I64, _P, _P],
     "dd_corner_turn": [_P, ctypes.c_int, _I64, _I32, _I64, _I32, _P, _I64, _P],
+    "dd_channelise": [_P, _I64, _I32, _I64, _I32, _P, _I64, _P],
     "dd_subband_plan_create": [_I32, _D, _D, _D, _I32, _P, _I32, _PP],
     "dd_subband_plan_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
     "dd_subband_dms": [_P, _P, _P],
@@ -564,3 +565,21 @@ class SubbandPlan:
             self.close()
         except Exception:
             pass
+
+
+def channelise(volt, nfft, out=None, stream=None):
+    """Section 5 front end: volt [nsamp, nsub] complex64 CUDA tensor (one
+    spectrum of coarse subbands per time sample) -> channel-ordered power
+    [nsub*nfft, nsamp // nfft] float32 (FFT of nfft samples per subband)."""
+    torch = _torch()
+    if volt.dim() != 2 or volt.dtype != torch.complex64 or volt.stride(1) != 1:
+        raise DedispError(DD_ERR_INVALID_ARG, "volt must be complex64 [nsamp, nsub], contiguous rows")
+    nsamp, nsub = volt.shape
+    nt = nsamp // int(nfft)
+    if out is None:
+        out = torch.empty((nsub * int(nfft), nt), dtype=torch.float32, device=volt.device)
+    if out.dim() != 2 or out.stride(1) != 1 or tuple(out.shape) != (nsub * int(nfft), nt):
+        raise DedispError(DD_ERR_INVALID_ARG, "out must be [nsub*nfft, nsamp//nfft]")
+    _check(lib().dd_channelise(volt.data_ptr(), nsamp, nsub, volt.stride(0), int(nfft),
+                               out.data_ptr(), out.stride(0), stream_handle(stream)))
+    return out

@@ -213,3 +213,64 @@ def serve_pulses(seed: int, npulses: int, period: int, dm_max: float = 500.0,
         out.append(dict(dm=dm, width=w, snr=s, amp=s / math.sqrt(nchans * w),
                         t0=int(g.integers(0, period))))
     return out
+
+
+# --------------------------------------------------------------------------
+# Section 5 front end: complex voltages of coarse subbands
+# --------------------------------------------------------------------------
+
+
+@dataclass(frozen=True)
+class FrontEnd:
+    """The toy observation of the real-time test (section 5): centre 610 MHz,
+    20 MHz bandwidth in `nsub` coarse subbands sampled every `t_samp` s, each
+    split into `nfft` channels by the front end; buffers of `nspec` spectra;
+    `ndms` DM trials up to `dm_max`."""
+    nsub: int = 256
+    f_centre: float = 610.0
+    bandwidth: float = 20.0
+    t_samp: float = 12.8e-6
+    nfft: int = 8
+    nspec: int = 1 << 19
+    ndms: int = 500
+    dm_max: float = 60.0
+    seed: int = 610
+
+    def band(self) -> Band:
+        """The channelised band: nsub*nfft channels of width bandwidth/(nsub*nfft),
+        sampled every nfft*t_samp.  Channel 0 is the highest FFT bin of the top
+        subband, one channel width below the band edge."""
+        nch = self.nsub * self.nfft
+        df = self.bandwidth / nch
+        return Band(nch, self.f_centre + self.bandwidth / 2 - df, df, self.t_samp * self.nfft)
+
+    def dms(self) -> np.ndarray:
+        return dm_grid(self.ndms, self.dm_max / self.ndms)
+
+
+def complex_noise(seed: int, nsamp: int, nsub: int) -> np.ndarray:
+    """[nsamp, nsub] complex64 with independent N(0, 1) real and imaginary
+    parts, drawn in one `standard_normal(dtype=float32)` call."""
+    v = np.empty((nsamp, nsub), dtype=np.complex64)
+    rng(seed).standard_normal(out=v.view(np.float32), dtype=np.float32)
+    return v
+
+
+def voltages_with_pulse(seed: int, nblocks: int, nsub: int, nfft: int, start: np.ndarray,
+                        width: int, amp: float) -> np.ndarray:
+    """Complex voltages [nblocks*nfft, nsub] whose length-nfft DFT per subband
+    and block, X[t, k, s], is complex Gaussian noise (unit variance per part)
+    with its power raised by the factor (1 + amp) for blocks start[s, k] <= t <
+    start[s, k] + width: a boxcar pulse whose arrival per subband and FFT bin
+    the caller gives.  The voltages are the inverse DFT of X along k (numpy's
+    ifft, 1/nfft normalisation), taken in chunks of blocks."""
+    X = complex_noise(seed, nblocks * nfft, nsub).reshape(nblocks, nfft, nsub)
+    gain = np.float32(math.sqrt(1.0 + amp))
+    for s in range(nsub):
+        for k in range(nfft):
+            a = int(start[s, k])
+            X[max(a, 0): max(a + width, 0), k, s] *= gain
+    step = 4096
+    for c in range(0, nblocks, step):
+        X[c: c + step] = np.fft.ifft(X[c: c + step], axis=1)
+    return X.reshape(nblocks * nfft, nsub)

@@ -138,3 +138,13 @@ def test_corner_turn_argument_errors_before_any_gpu_work():
     assert L.dd_corner_turn(a, dd.DD_U8, 10, 4, 4, 0, b, 9, None) == dd.DD_ERR_INVALID_ARG
     assert L.dd_corner_turn(a, dd.DD_I32, 10, 4, 4, 0, b, 10, None) == dd.DD_ERR_DTYPE
     assert L.dd_corner_turn(a, dd.DD_F32, 10, 4, 4, 0, ctypes.c_void_p(0x1010), 10, None) == dd.DD_ERR_INVALID_ARG
+
+
+def test_channelise_argument_errors_before_any_gpu_work():
+    L = dd.lib()
+    a = ctypes.c_void_p(0x1000)
+    assert L.dd_channelise(None, 64, 4, 4, 8, a, 8, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_channelise(a, 64, 4, 3, 8, a, 8, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_channelise(a, 64, 4, 4, 8, a, 7, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_channelise(a, 64, 4, 4, 3, a, 64, None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_channelise(a, 64, 4, 4, 32, a, 64, None) == dd.DD_ERR_INVALID_ARG
