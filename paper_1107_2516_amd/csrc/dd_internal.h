@@ -91,9 +91,10 @@ dd_status plan_from_table(int32_t nchans, int32_t ndms, const int32_t* delays, d
 
 // Uploads (once per device) and returns the tile tables for height td.
 dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out);
-// Per (tile, channel, DM) dword offsets for the aligned-copies kernels: with
-// a = base & (epd-1) and R = a + rel, the DM reads copy R mod epd at dword
-// R / epd, i.e. offset (R mod epd) * slotd + R / epd within the channel.
+// Per (tile, channel, DM) byte offsets for the aligned-copies kernels, as
+// uint16 (the buffer is returned as int32_t*): with a = base & (epd-1) and
+// R = a + rel, the DM reads copy R mod epd at dword R / epd, i.e. byte
+// 4 * ((R mod epd) * slotd + R / epd) within the channel.
 dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** out);
 // Per (tile, channel, DM) shifts relative to the channel's window start
 // rounded down to a whole dword: rel + (base & (epd-1)).

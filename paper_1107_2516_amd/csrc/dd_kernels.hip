@@ -281,15 +281,17 @@ struct BodyWin {
 // (ds_read2st64_b32, 64 consecutive dwords per wavefront).  Copy 0 is written
 // by asynchronous buffer loads straight into LDS; copies 1..EPD-1 are built
 // from it with v_alignbyte_b32 once it lands; both are double-buffered by
-// stage.  The dword offset of every (tile, channel, DM) within the channel's
-// copies is precomputed on the host (plan_aoff), so the per-DM work in the
-// loop is one address add and the reads.
+// stage.  The byte offset of every (tile, channel, DM) within the channel's
+// copies is precomputed on the host (plan_aoff, 16 bits each, two per table
+// word, so a wavefront holds a channel's offsets in DW/2 registers), and the
+// per-DM work in the loop is one address add and the reads.
 //
 // Accumulation:
-//  * u8: SWAR in fast VOP2 instructions: e = x & 0x00ff00ff and
-//    o = (x >> 8) & 0x00ff00ff each hold two samples in 16-bit lanes and are
-//    added into 16-bit-lane accumulators, emptied into the int32 output every
-//    256 channels (255 * 256 < 2^16, so no lane ever carries; the first time
+//  * u8: SWAR: e = x & 0x00ff00ff and o = (x >> 8) & 0x00ff00ff (one
+//    v_perm_b32) each hold two samples in 16-bit lanes; two channels' words
+//    are added into 16-bit-lane accumulators by one v_add3_u32, and the
+//    accumulators are emptied into the int32 output at least every 256
+//    channels (255 * 256 < 2^16, so no lane ever carries; the first time
 //    stored, then added: the workgroup owns those outputs).
 //  * f16: v_fma_mix_f32 (x * 1.0 + acc with x an f16 half; the product is
 //    exact), one instruction per sample, FP32 accumulation.
@@ -314,7 +316,7 @@ struct BodyCopies {
     const int tail = static_cast<int>(p.nsamp % EPD);         // samples in the partial dword
     const int chan_dw = EPD * slotd;  // LDS: [buffer][stage channel][copy][slotd]
     const int tabd = table_dwords(cc_max);  // then [buffer][stage channel][TD] offsets
-    int32_t* tabl = reinterpret_cast<int32_t*>(lds + 2 * cc_max * chan_dw);
+    uint32_t* tabl = lds + 2 * cc_max * chan_dw;
     auto window_dword = [&](int c) -> int {
       return static_cast<int>(
           (t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
@@ -335,11 +337,12 @@ struct BodyCopies {
       }
       // the stage's copy offsets, [channel][TD], staged beside the data
       if (wave == 3) {
-        const int32_t* t0p = p.tab + (static_cast<int64_t>(dtile) * p.nchans + c0) * TD;
+        const uint16_t* t0p = reinterpret_cast<const uint16_t*>(p.tab) +
+                              (static_cast<int64_t>(dtile) * p.nchans + c0) * TD;
         __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<int32_t*>(t0p), 0, ncc * TD * 4, 0x00020000);
-        int32_t* dst = tabl + buf * tabd;
-        for (int e = 0; e < ncc * TD; e += 64)
+            const_cast<uint16_t*>(t0p), 0, ncc * TD * 2, 0x00020000);
+        uint32_t* dst = tabl + buf * tabd;
+        for (int e = 0; e < ncc * TD / 2; e += 64)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
               rt, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(e + lane) * 4u, 0, 0, 0);
       }
@@ -428,20 +431,78 @@ struct BodyCopies {
       if (s + 1 < nstage) issue(s + 1, buf ^ 1);
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
-      const int32_t* tb = tabl + buf * tabd + wave * DW;
-      int o[DW];
+      // this wave's DW offsets of stage channel i: DW/2 words of two
+      // 16-bit byte offsets each
+      const uint32_t* tb = tabl + buf * tabd + wave * (DW / 2);
+      constexpr int TW = TD / 2;  // table words per channel
+      auto off = [](const uint32_t (&w)[DW / 2], int j) -> int {
+        return static_cast<int>((w[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+      };
+      uint32_t o[DW / 2];
 #pragma unroll
-      for (int j = 0; j < DW; j++) o[j] = tb[j];
-      for (int i = 0; i < ncc; i++) {
-        int on[DW];  // next channel's offsets: an LDS read issued behind this channel's
-        const int32_t* tn = tb + min(i + 1, ncc - 1) * TD;
+      for (int k = 0; k < DW / 2; k++) o[k] = tb[k];
+      int i = 0;
+      if constexpr (EPD == 4) {
+        // u8, two channels per step: their masked words go into one
+        // three-input add per 16-bit-lane accumulator.  The step's offsets
+        // are read at its top and the other resident wavefronts cover that
+        // latency (reading them a step ahead measured no faster).
+        auto step2 = [&](int c, const uint32_t (&w0)[DW / 2], const uint32_t (&w1)[DW / 2]) {
+          // the lane's byte address in channel c's copies, kept opaque so that
+          // each DM's address is one add
+          uint32_t lb = static_cast<uint32_t>(((buf * cc_max + c) * chan_dw + lane) * 4);
+          asm volatile("" : "+v"(lb));
+          const unsigned char* b0 = reinterpret_cast<const unsigned char*>(lds) + lb;
+          const unsigned char* b1 = b0 + chan_dw * 4;
 #pragma unroll
-        for (int j = 0; j < DW; j++) on[j] = tn[j];
-        const int chan_off = (buf * cc_max + i) * chan_dw;
+          for (int j = 0; j < DW; j++) {
+            const uint32_t* s0 = reinterpret_cast<const uint32_t*>(b0 + off(w0, j));
+            const uint32_t* s1 = reinterpret_cast<const uint32_t*>(b1 + off(w1, j));
+#pragma unroll
+            for (int ii = 0; ii < I; ii++) {
+              const uint32_t a = s0[64 * ii], b = s1[64 * ii];
+              acc[j][ii][0] += (a & 0x00ff00ffu) + (b & 0x00ff00ffu);
+              // bytes 1 and 3 into the low bytes of the 16-bit lanes
+              acc[j][ii][1] += __builtin_amdgcn_perm(0u, a, 0x0c030c01u) +
+                               __builtin_amdgcn_perm(0u, b, 0x0c030c01u);
+            }
+          }
+          since_flush += 2;
+          if (since_flush > 254) {
+            flush();
+            since_flush = 0;
+          }
+        };
+        auto read2 = [&](int c, uint32_t (&w0)[DW / 2], uint32_t (&w1)[DW / 2]) {
+          const uint32_t* t0 = tb + min(c, ncc - 1) * TW;
+          const uint32_t* t1 = tb + min(c + 1, ncc - 1) * TW;
+#pragma unroll
+          for (int k = 0; k < DW / 2; k++) {
+            w0[k] = t0[k];
+            w1[k] = t1[k];
+          }
+        };
+        for (; i + 1 < ncc; i += 2) {
+          uint32_t a0[DW / 2], a1[DW / 2];
+          read2(i, a0, a1);
+          step2(i, a0, a1);
+        }
+        if (i < ncc) {
+#pragma unroll
+          for (int k = 0; k < DW / 2; k++) o[k] = tb[i * TW + k];
+        }
+      }
+      for (; i < ncc; i++) {
+        uint32_t on[DW / 2];  // next channel's offsets: an LDS read issued behind this channel's
+        const uint32_t* tn = tb + min(i + 1, ncc - 1) * TW;
+#pragma unroll
+        for (int k = 0; k < DW / 2; k++) on[k] = tn[k];
+        const unsigned char* b0 =
+            reinterpret_cast<const unsigned char*>(lds + (buf * cc_max + i) * chan_dw + lane);
         uint32_t xs[DW][I];
 #pragma unroll
         for (int j = 0; j < DW; j++) {
-          const uint32_t* src = lds + chan_off + o[j] + lane;
+          const uint32_t* src = reinterpret_cast<const uint32_t*>(b0 + off(o, j));
 #pragma unroll
           for (int ii = 0; ii < I; ii++) xs[j][ii] = src[64 * ii];
         }
@@ -465,13 +526,13 @@ struct BodyCopies {
           }
         }
         if constexpr (EPD == 4) {
-          if (++since_flush == 256) {
+          if (++since_flush > 254) {
             flush();
             since_flush = 0;
           }
         }
 #pragma unroll
-        for (int j = 0; j < DW; j++) o[j] = on[j];
+        for (int k = 0; k < DW / 2; k++) o[k] = on[k];
       }
     }
     if constexpr (EPD == 4) {
@@ -507,7 +568,7 @@ struct BodyCopies {
   }
   // LDS dwords for one buffer of a stage's copy offsets, whole 64-dword
   // DMA instructions
-  __host__ __device__ static constexpr int table_dwords(int cc) { return (cc * TD + 63) & ~63; }
+  __host__ __device__ static constexpr int table_dwords(int cc) { return (cc * TD / 2 + 63) & ~63; }
   static constexpr int table_epd = EPD;
 };
 

@@ -175,7 +175,7 @@ dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** o
   const int nch = plan->nchans;
   const int ntiles = tt->ntiles;
   const int sh = epd == 4 ? 2 : (epd == 2 ? 1 : 0);
-  std::vector<int32_t> host(static_cast<size_t>(ntiles) * nch * td + 8, 0);
+  std::vector<uint16_t> host(static_cast<size_t>(ntiles) * nch * td + 16, 0);
   for (int tile = 0; tile < ntiles; tile++) {
     const int first = tile * td;
     const int count = std::min(td, plan->ndms - first);
@@ -187,14 +187,16 @@ dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** o
       for (int j = 0; j < td; j++) {
         const int src = plan->order[first + (j < count ? j : 0)];
         const int R = a + plan->delays[static_cast<size_t>(src) * nch + c] - lo;
-        host[(static_cast<size_t>(tile) * nch + c) * td + j] = (R & (epd - 1)) * slotd + (R >> sh);
+        const int64_t b = 4 * (static_cast<int64_t>(R & (epd - 1)) * slotd + (R >> sh));
+        if (b > 0xffff) return set_error(DD_ERR_TOO_LARGE, "copy offset beyond 16 bits");
+        host[(static_cast<size_t>(tile) * nch + c) * td + j] = static_cast<uint16_t>(b);
       }
     }
   }
   int32_t* d = nullptr;
-  hipError_t e = hipMalloc(&d, host.size() * sizeof(int32_t));
+  hipError_t e = hipMalloc(&d, host.size() * sizeof(uint16_t));
   if (e == hipSuccess)
-    e = hipMemcpy(d, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(d, host.data(), host.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d);
     return hip_error(e, "uploading copy offsets");

@@ -270,6 +270,27 @@ def test_pair_window_flushes(tsamp, dw):
     assert np.array_equal(y.cpu().numpy().astype(np.int64), oracle.dedisperse(x, tab))
 
 
+@pytest.mark.parametrize("dw,tsamp,cc", [(8, 8, 8), (8, 8, 7), (4, 16, 5), (8, 16, 3)])
+def test_copies_flush_full_scale(dw, tsamp, cc):
+    """8-bit aligned-copies kernel over 1001 channels of full-scale samples:
+    channels are summed two at a time with single channels where a stage has
+    an odd count, and every 16-bit lane reaches 255*256 before it is emptied
+    into the output."""
+    g = np.random.default_rng(900 + dw + tsamp + cc)
+    nchans, ndms, nsamp = 1001, 40, 4001
+    tab = np.sort(rand_table(g, ndms, nchans, 700), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    x = np.full((nchans, nsamp), 255, dtype=np.uint8)
+    x[::5, 900:1500] = g.integers(0, 256, size=x[::5, 900:1500].shape, dtype=np.uint8)
+    stride = (nsamp + 3) // 4 * 4
+    big = np.zeros((nchans, stride), dtype=np.uint8)
+    big[:, :nsamp] = x
+    tile = dict(variant=3, dms_per_wave=dw, waves=4, tsamp_per_lane=tsamp, chans_per_stage=cc)
+    y = plan.execute_tiled(torch.from_numpy(big).cuda()[:, :nsamp], tile)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().astype(np.int64), oracle.dedisperse(x, tab))
+
+
 @pytest.mark.parametrize("dtype", ["u8", "f16"])
 def test_unaligned_rows_fall_back(dtype):
     """Rows that do not start on a dword boundary take the LDS-streaming
