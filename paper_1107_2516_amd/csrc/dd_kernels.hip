@@ -278,10 +278,12 @@ struct BodyWin {
 // whose shift is not a multiple of EPD would need every dword realigned;
 // instead the workgroup keeps EPD copies of each staged channel, copy m
 // shifted by m samples, so every DM reads whole aligned dwords
-// (ds_read2st64_b32, 64 consecutive dwords per wavefront).  Copy 0 is written
-// by asynchronous buffer loads straight into LDS; copies 1..EPD-1 are built
-// from it with v_alignbyte_b32 once it lands; both are double-buffered by
-// stage.  The byte offset of every (tile, channel, DM) within the channel's
+// (ds_read2st64_b32, 64 consecutive dwords per wavefront).  A stage's rows
+// land by asynchronous buffer loads straight into a raw area of LDS (the next
+// stage's loads overlap the current stage's sums); after a barrier all EPD
+// copies are built from it with v_alignbyte_b32.  Only the raw area is
+// double-buffered in effect, so a stage holds EPD+1 rows per channel instead
+// of 2*EPD, and more channels fit between barriers.  The byte offset of every (tile, channel, DM) within the channel's
 // copies is precomputed on the host (plan_aoff, 16 bits each, two per table
 // word, so a wavefront holds a channel's offsets in DW/2 registers), and the
 // per-DM work in the loop is one address add and the reads.
@@ -314,9 +316,14 @@ struct BodyCopies {
     const int64_t row_bytes = p.in_stride * static_cast<int64_t>(sizeof(Tin));
     const int full_dwords = static_cast<int>(p.nsamp / EPD);  // dwords wholly inside a row
     const int tail = static_cast<int>(p.nsamp % EPD);         // samples in the partial dword
-    const int chan_dw = EPD * slotd;  // LDS: [buffer][stage channel][copy][slotd]
-    const int tabd = table_dwords(cc_max);  // then [buffer][stage channel][TD] offsets
-    uint32_t* tabl = lds + 2 * cc_max * chan_dw;
+    // LDS: the copies [stage channel][copy][slotd] (one stage), the raw rows
+    // of the next stage [stage channel][slotd] (the buffer loads land there
+    // while the current stage is summed), then [buffer][stage channel][TD]
+    // table offsets
+    const int chan_dw = EPD * slotd;
+    const int tabd = table_dwords(cc_max);
+    uint32_t* raw = lds + cc_max * chan_dw;
+    uint32_t* tabl = raw + cc_max * slotd;
     auto window_dword = [&](int c) -> int {
       return static_cast<int>(
           (t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> SH);
@@ -330,7 +337,7 @@ struct BodyCopies {
         __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<unsigned char*>(in + static_cast<int64_t>(c) * row_bytes), 0,
             full_dwords * 4, 0x00020000);
-        uint32_t* dst = lds + (buf * cc_max + i) * chan_dw;
+        uint32_t* dst = raw + i * slotd;
         for (int e = 0; e < slotd; e += 64)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
               rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
@@ -357,25 +364,26 @@ struct BodyCopies {
         v |= static_cast<uint32_t>(row[k]) << (8 * k);
       return v;
     };
-    auto build = [&](int s, int buf) {
+    auto build = [&](int s) {
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
       for (int i = 0; i < ncc; i++) {
         const int c = c0 + i;
-        uint32_t* d0 = lds + (buf * cc_max + i) * chan_dw;
+        const uint32_t* r0 = raw + i * slotd;
+        uint32_t* d0 = lds + i * chan_dw;
         const int tl = full_dwords - window_dword(c);  // window index of the partial dword
-        for (int e = tid; e < slotd - 1; e += 256) {
-          uint32_t lo = d0[e], hi = d0[e + 1];
+        for (int e = tid; e < slotd; e += 256) {
+          uint32_t lo = r0[e], hi = e + 1 < slotd ? r0[e + 1] : 0u;
           if (tail) {
             if (e == tl) lo = tail_dword(c);
             if (e + 1 == tl) hi = tail_dword(c);
           }
+          d0[e] = lo;
 #pragma unroll
           for (int m = 1; m < EPD; m++)
             d0[m * slotd + e] =
                 __builtin_amdgcn_alignbyte(hi, lo, m * static_cast<int>(sizeof(Tin)));
         }
-        if (tail && tl >= 0 && tl < slotd && (tl & 255) == tid) d0[tl] = tail_dword(c);
       }
     };
 
@@ -425,9 +433,9 @@ struct BodyCopies {
     for (int s = 0; s < nstage; s++) {
       const int buf = s & 1;
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();  // copy 0 of stage s landed; every wave is done with stage s-1
-      build(s, buf);
-      __syncthreads();  // shifted copies of stage s are ready
+      __syncthreads();  // raw rows of stage s landed; every wave is done with stage s-1
+      build(s);
+      __syncthreads();  // the copies of stage s are ready and the raw area is free
       if (s + 1 < nstage) issue(s + 1, buf ^ 1);
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
@@ -450,7 +458,7 @@ struct BodyCopies {
         auto step2 = [&](int c, const uint32_t (&w0)[DW / 2], const uint32_t (&w1)[DW / 2]) {
           // the lane's byte address in channel c's copies, kept opaque so that
           // each DM's address is one add
-          uint32_t lb = static_cast<uint32_t>(((buf * cc_max + c) * chan_dw + lane) * 4);
+          uint32_t lb = static_cast<uint32_t>((c * chan_dw + lane) * 4);
           asm volatile("" : "+v"(lb));
           const unsigned char* b0 = reinterpret_cast<const unsigned char*>(lds) + lb;
           const unsigned char* b1 = b0 + chan_dw * 4;
@@ -497,8 +505,7 @@ struct BodyCopies {
         const uint32_t* tn = tb + min(i + 1, ncc - 1) * TW;
 #pragma unroll
         for (int k = 0; k < DW / 2; k++) on[k] = tn[k];
-        const unsigned char* b0 =
-            reinterpret_cast<const unsigned char*>(lds + (buf * cc_max + i) * chan_dw + lane);
+        const unsigned char* b0 = reinterpret_cast<const unsigned char*>(lds + i * chan_dw + lane);
         uint32_t xs[DW][I];
 #pragma unroll
         for (int j = 0; j < DW; j++) {
@@ -555,7 +562,7 @@ struct BodyCopies {
   static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
     // dwords read per copy: 64*I for the tile + shift spread + alignment, +1 for the builder
     const int s = (64 * I + (span_max + EPD - 1 + EPD - 1) / EPD + 1 + 63) & ~63;
-    const size_t per_chan = static_cast<size_t>(s) * 4 * EPD * 2;
+    const size_t per_chan = static_cast<size_t>(s) * 4 * (EPD + 1);  // copies + raw rows
     const size_t budget = 160 * 1024 / OCC;
     auto total = [&](int c) { return per_chan * c + 2 * static_cast<size_t>(table_dwords(c)) * 4; };
     if (total(1) > budget) return -1;

@@ -206,6 +206,7 @@ TILES_COPIES = [
     ("u8", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)),
     ("u8", dict(variant=3, dms_per_wave=4, waves=4, tsamp_per_lane=16, chans_per_stage=8)),
     ("u8", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=4)),
+    ("u8", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=8)),
     ("f16", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)),
     ("f16", dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=4, chans_per_stage=8)),
     ("u8", dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=28, chans_per_stage=8)),
