@@ -67,6 +67,8 @@ struct DeviceTables {
   std::map<std::tuple<int, int, int>, int32_t*> aoff;
   // rel + (base mod samples per dword), keyed by (td, samples per dword)
   std::map<std::pair<int, int>, int32_t*> ralign;
+  // scheduled register-window entries, keyed by (td, DMs per wave, slack)
+  std::map<std::tuple<int, int, int>, int32_t*> wintab;
 };
 
 }  // namespace dd
@@ -99,6 +101,14 @@ dd_status plan_aoff(dd_plan* plan, int td, int epd, int slotd, const int32_t** o
 // Per (tile, channel, DM) shifts relative to the channel's window start
 // rounded down to a whole dword: rel + (base & (epd-1)).
 dd_status plan_ralign(dd_plan* plan, int td, int epd, const int32_t** out);
+// Register-window schedule per (tile, channel, DM) for the scheduled FP32
+// kernel: the DMs of a wavefront are dw consecutive tile rows; DM 0 of each
+// wavefront loads the window at its shift rounded down to 4 samples, and a
+// later DM reloads it when its shift lies outside [start, start + slack].
+// Entry = ix | start << 16 | reload << 31, with ix = shift - start (<= slack,
+// bits 8-15 zero) and start < 2^14; on DM 0, bit 30 is set when a later DM
+// of the wavefront reloads.
+dd_status plan_wintab(dd_plan* plan, int td, int dw, int slack, const int32_t** out);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {

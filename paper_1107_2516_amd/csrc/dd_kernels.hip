@@ -50,7 +50,8 @@ struct KParams {
   void* out;
   int64_t out_stride, nout;
   const int32_t* base;  // [tile][nchans]
-  const int32_t* tab;   // rel (variants 0-2) or copy offsets (variant 3), [tile][nchans][TD]
+  const int32_t* tab;   // [tile][nchans][TD]: rel (variants 0-2), copy offsets (3),
+                        // aligned rel (4) or scheduled window entries (5)
   const int32_t* rows;  // [tile][TD]
   int32_t nchans, slot, cc;
   int32_t n_dtiles, n_ttiles, nblocks, per_xcd;
@@ -188,7 +189,7 @@ struct BodyLds {
 // row bounds reads at nsamp samples, so samples past the end read as zero
 // (they only feed outputs t >= nout, which are not stored).
 template <int DW, int K, int WMAX, int OCC_,
-          void (*STEP)(float*, const int*, unsigned, const int32_t*, int*)>
+          void (*STEP)(float*, const int*, unsigned, const int32_t*, int*), bool SCHED = false>
 struct BodyWin {
   static constexpr int TD = 4 * DW, TT = 64 * K, OCC = OCC_;
   __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
@@ -268,6 +269,8 @@ struct BodyWin {
     return 0;
   }
   static constexpr int table_epd = 0;
+  // variant 5: the step reads host-scheduled window entries (plan_wintab)
+  static constexpr int table_win = SCHED ? WMAX - K : 0;
 };
 
 // ---------------------------------------------------------------- variant 3
@@ -861,7 +864,7 @@ struct Impl {
   int (*geometry)(int span_max, int cc_req, int* slot, int* cc, size_t* lds);
   const void* single;
   const void* batch;
-  int td, tt, table_epd, table_ralign;
+  int td, tt, table_epd, table_ralign, table_win;
   size_t in_size;
   bool needs_dword_rows;
 };
@@ -875,6 +878,15 @@ struct RalignOf<Body, std::void_t<decltype(Body::table_ralign)>> {
   static constexpr int value = Body::table_ralign;
 };
 
+template <class Body, class = void>
+struct WinOf {
+  static constexpr int value = 0;
+};
+template <class Body>
+struct WinOf<Body, std::void_t<decltype(Body::table_win)>> {
+  static constexpr int value = Body::table_win;
+};
+
 template <class Body, typename Tin>
 Impl make_impl() {
   Impl m;
@@ -885,6 +897,7 @@ Impl make_impl() {
   m.tt = Body::TT;
   m.table_epd = Body::table_epd;
   m.table_ralign = RalignOf<Body>::value;
+  m.table_win = WinOf<Body>::value;
   m.in_size = sizeof(Tin);
   m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0;
   return m;
@@ -909,6 +922,18 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
       return *out = make_impl<BodyWin<6, 12, 64, 3, dd_f32_d6_k12_w64_channel>, float>(), true;
     if (d == 4 && k == 12)
       return *out = make_impl<BodyWin<4, 12, 40, 4, dd_f32_d4_k12_w40_channel>, float>(), true;
+  }
+  if (in_t == DD_F32 && v == 5) {
+    if (d == 8 && k == 20)
+      return *out = make_impl<BodyWin<8, 20, 56, 2, dd_s_f32_d8_k20_w56_channel, true>, float>(), true;
+    if (d == 8 && k == 12)
+      return *out = make_impl<BodyWin<8, 12, 48, 3, dd_s_f32_d8_k12_w48_channel, true>, float>(), true;
+    if (d == 4 && k == 20)
+      return *out = make_impl<BodyWin<4, 20, 56, 3, dd_s_f32_d4_k20_w56_channel, true>, float>(), true;
+    if (d == 6 && k == 12)
+      return *out = make_impl<BodyWin<6, 12, 64, 3, dd_s_f32_d6_k12_w64_channel, true>, float>(), true;
+    if (d == 4 && k == 12)
+      return *out = make_impl<BodyWin<4, 12, 40, 4, dd_s_f32_d4_k12_w40_channel, true>, float>(), true;
   }
   if (in_t == DD_F32 && v == 2) {
     if (d == 8 && k == 20)
@@ -991,6 +1016,18 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
     if (st != DD_OK) return st;
   } else if (impl.table_ralign) {
     st = plan_ralign(a.plan, impl.td, impl.table_ralign, &tab);
+    if (st != DD_OK) return st;
+  } else if (impl.table_win) {
+    st = plan_wintab(a.plan, impl.td, impl.td / 4, impl.table_win, &tab);
+    if (st == DD_ERR_TOO_LARGE) {
+      // window starts beyond the schedule's 14 bits: the same tile with the
+      // run-time window logic (same body parameters, so the same geometry)
+      TileShape s1 = s;
+      s1.variant = 1;
+      if (!find_impl(s1, in_t, &impl)) return st;
+      tab = tt->d_rel;
+      st = DD_OK;
+    }
     if (st != DD_OK) return st;
   }
   const int64_t n_ttiles = (a.nout + impl.tt - 1) / impl.tt;
@@ -1077,6 +1114,8 @@ dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams
     PreparedLaunch pl;
     dd_status st = prepare(s, in_t, beams[i], &pl);
     if (st != DD_OK) return st;
+    if (i > 0 && pl.impl.batch != impl.batch)
+      return set_error(DD_ERR_TOO_LARGE, "beams need different kernels for this shape");
     impl = pl.impl;
     std::memcpy(out->params.data() + static_cast<size_t>(i) * sizeof(KParams), &pl.p,
                 sizeof(KParams));

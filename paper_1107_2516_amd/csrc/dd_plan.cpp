@@ -250,6 +250,67 @@ dd_status plan_ralign(dd_plan* plan, int td, int epd, const int32_t** out) {
   return DD_OK;
 }
 
+dd_status plan_wintab(dd_plan* plan, int td, int dw, int slack, const int32_t** out) {
+  if (dw < 1 || td % dw != 0 || slack < 3 || slack > 255)
+    return set_error(DD_ERR_INVALID_ARG, "bad window schedule shape");
+  const TileTables* tt = nullptr;
+  dd_status st = plan_tiles(plan, td, &tt);
+  if (st != DD_OK) return st;
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceTables& dt = plan->dev[dev];
+  const auto key = std::make_tuple(td, dw, slack);
+  auto it = dt.wintab.find(key);
+  if (it != dt.wintab.end()) {
+    *out = it->second;
+    return DD_OK;
+  }
+  const int nch = plan->nchans;
+  const int ntiles = tt->ntiles;
+  std::vector<int32_t> host(static_cast<size_t>(ntiles) * nch * td + 8, 0);
+  for (int tile = 0; tile < ntiles; tile++) {
+    const int first = tile * td;
+    const int count = std::min(td, plan->ndms - first);
+    for (int c = 0; c < nch; c++) {
+      int32_t lo = INT32_MAX;
+      for (int j = 0; j < count; j++)
+        lo = std::min(lo, plan->delays[static_cast<size_t>(plan->order[first + j]) * nch + c]);
+      int32_t* e = &host[(static_cast<size_t>(tile) * nch + c) * td];
+      for (int w = 0; w < td / dw; w++) {
+        int32_t start = 0;
+        bool later = false;
+        for (int j = 0; j < dw; j++) {
+          const int q = w * dw + j;
+          const int src = plan->order[first + (q < count ? q : 0)];
+          const int32_t r = plan->delays[static_cast<size_t>(src) * nch + c] - lo;
+          const bool reload =
+              j == 0 || static_cast<uint32_t>(r - start) > static_cast<uint32_t>(slack);
+          if (reload) start = r & ~3;
+          if (start >= (1 << 14))
+            return set_error(DD_ERR_TOO_LARGE, "shift spread too large for the window schedule");
+          later = later || (reload && j > 0);
+          e[q] = static_cast<int32_t>(static_cast<uint32_t>(r - start) |
+                                      (static_cast<uint32_t>(start) << 16) |
+                                      (reload ? 0x80000000u : 0u));
+        }
+        if (later) e[w * dw] = static_cast<int32_t>(static_cast<uint32_t>(e[w * dw]) | 0x40000000u);
+      }
+    }
+  }
+  int32_t* d = nullptr;
+  hipError_t err = hipMalloc(&d, host.size() * sizeof(int32_t));
+  if (err == hipSuccess)
+    err = hipMemcpy(d, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(d);
+    return hip_error(err, "uploading the window schedule");
+  }
+  dt.wintab.emplace(key, d);
+  *out = d;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 dd_plan::~dd_plan() {
@@ -264,6 +325,7 @@ dd_plan::~dd_plan() {
     }
     for (auto& t : kv.second.aoff) (void)hipFree(t.second);
     for (auto& t : kv.second.ralign) (void)hipFree(t.second);
+    for (auto& t : kv.second.wintab) (void)hipFree(t.second);
     (void)hipSetDevice(cur);
   }
 }

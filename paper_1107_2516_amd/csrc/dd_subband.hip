@@ -95,7 +95,7 @@ size_t params_workspace(const dd_subband_plan* sp) {
 // register-window DM tile that holds them
 dd::TileShape stage_shape(int rows) {
   dd::TileShape s;
-  s.variant = 1;
+  s.variant = 5;
   s.waves = 4;
   s.tsamp_per_lane = 12;
   s.chans_per_stage = 8;

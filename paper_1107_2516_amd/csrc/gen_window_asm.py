@@ -109,6 +109,81 @@ def gen(name, dw, k, wmax, occ):
     return "\n".join(out)
 
 
+def gen_sched(name, dw, k, wmax, occ):
+    """Scheduled flavour: the host has already run the window logic (plan
+    table "wintab"), so each DM's table entry holds its window index ix
+    (bits 0-7; bits 8-15 are zero), the window start for a reload (bits
+    16-29), a reload flag (bit 31) and, on DM 0, whether any later DM of the
+    wavefront reloads at this channel (bit 30).  DM 0 always loads the window.  When no later DM
+    reloads (the common case once the shift spread of the wavefront's DMs is
+    below WMAX-K), the DMs run back to back inside one indexing region, each
+    switching only the index (s_set_gpr_idx_idx reads entry bits 0-7); the
+    other channels take the per-DM path with a reload test on bit 31."""
+    assert k % 4 == 0 and wmax % 4 == 0 and wmax >= k + 4 and wmax - k <= 255
+    wb = vgpr_budget(occ) - wmax
+    out = []
+    out.append(f"// s_{name}: DW={dw} K={k} WMAX={wmax} OCC={occ}, window v{wb}..v{wb + wmax - 1}, "
+               f"host-scheduled reloads")
+    out.append(f"__device__ __forceinline__ void dd_s_{name}_channel(float* acc, const int* r, unsigned addr, const int32_t* next, int* rn) {{")
+    vec = "int4v" if dw <= 4 else "int8v"
+    out += ["  int tb;", "  unsigned va;", f"  {vec} nv;"]
+    out.append("  asm volatile(")
+
+    def reload(j):
+        lines = [f'      "s_bfe_u32 %[tb], %[r{j}], 0xe0010\\n"',  # bits 16..29: window start
+                 '      "s_lshl_b32 %[tb], %[tb], 2\\n"',
+                 '      "v_add_u32 %[va], %[tb], %[addr]\\n"']
+        for i in range(wmax // 4):
+            off = f" offset:{16 * i}" if i else ""
+            lines.append(f'      "ds_read_b128 v[{wb + 4 * i}:{wb + 4 * i + 3}], %[va]{off}\\n"')
+        lines.append('      "s_waitcnt lgkmcnt(0)\\n"')
+        return lines
+
+    def adds(j):
+        return [f'      "v_add_f32 %[a{j}_{kk}], v{wb + kk}, %[a{j}_{kk}]\\n"' for kk in range(k)]
+
+    out += reload(0)
+    out.append('      "s_set_gpr_idx_on %[r0], gpr_idx(SRC0)\\n"')
+    out.append('      "s_nop 0\\n"')
+    out += adds(0)
+    out.append(prefetch_issue(dw))
+    if dw > 1:
+        out.append('      "s_bitcmp1_b32 %[r0], 30\\n"')
+        out.append('      "s_cbranch_scc1 .Lslow_%=\\n"')
+        for j in range(1, dw):
+            out.append(f'      "s_set_gpr_idx_idx %[r{j}]\\n"')
+            out.append('      "s_nop 0\\n"')
+            out += adds(j)
+        out.append('      "s_branch .Ldone_%=\\n"')
+        out.append('      ".Lslow_%=:\\n"')
+        for j in range(1, dw):
+            out.append(f'      "s_bitcmp1_b32 %[r{j}], 31\\n"')
+            out.append(f'      "s_cbranch_scc0 .Lkeep_%=_{j}\\n"')
+            out.append('      "s_set_gpr_idx_off\\n"')
+            out += reload(j)
+            out.append(f'      "s_set_gpr_idx_on %[r{j}], gpr_idx(SRC0)\\n"')
+            out.append(f'      ".Lkeep_%=_{j}:\\n"')
+            out.append(f'      "s_set_gpr_idx_idx %[r{j}]\\n"')
+            out.append('      "s_nop 0\\n"')
+            out += adds(j)
+        out.append('      ".Ldone_%=:\\n"')
+    out.append('      "s_set_gpr_idx_off\\n"')
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+    outs = []
+    for j in range(dw):
+        for kk in range(k):
+            outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
+    outs += ['[tb] "=&s"(tb)', '[va] "=&v"(va)', '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)'] + [f'[r{j}] "s"(r[{j}])' for j in range(dw)]
+    clob = [f'"v{wb + i}"' for i in range(wmax)] + ['"m0"', '"scc"', '"memory"']
+    out.append("      : " + ",\n        ".join(outs))
+    out.append("      : " + ", ".join(ins))
+    out.append("      : " + ", ".join(clob) + ");")
+    out += prefetch_store(dw)
+    out.append("}")
+    return "\n".join(out)
+
+
 JT_CONFIGS = [
     # jump-table flavour: name, DMs per wave, samples per lane, window, waves per SIMD
     ("jt_f32_d8_k20_w56", 8, 20, 56, 2),
@@ -256,6 +331,9 @@ def main():
     print("typedef int int8v __attribute__((ext_vector_type(8)));")
     for cfg in CONFIGS:
         print(gen(*cfg))
+        print()
+    for cfg in CONFIGS:
+        print(gen_sched(*cfg))
         print()
     for cfg in JT_CONFIGS:
         print(gen_jt(*cfg))

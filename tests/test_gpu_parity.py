@@ -181,6 +181,11 @@ TILES_F32 = [
     dict(variant=2, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
     dict(variant=2, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
     dict(variant=2, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
+    dict(variant=5, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
+    dict(variant=5, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=5, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
+    dict(variant=5, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=5, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
 ]
 TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}".format(**t) for t in TILES_F32]
 
