@@ -974,7 +974,7 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
                               _Float16>(), true;
   }
   if (in_t == DD_F16 && v == 3) {
-    if (d == 8 && k == 8) return *out = make_impl<BodyCopies<_Float16, 8, 4, 4>, _Float16>(), true;
+    if (d == 8 && k == 8) return *out = make_impl<BodyCopies<_Float16, 8, 4, 5>, _Float16>(), true;
     if (d == 8 && k == 4) return *out = make_impl<BodyCopies<_Float16, 8, 2, 4>, _Float16>(), true;
   }
   return false;
