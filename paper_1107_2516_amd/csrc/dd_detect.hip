@@ -87,12 +87,17 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
                                                      int64_t max_events,
                                                      unsigned long long* __restrict__ count) {
   __shared__ __align__(16) float y[kLds];
+  __shared__ float s_inv[8];
   const int d = blockIdx.y;
   const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTile;
   const double mu = stats[2 * d];
   const double sg = stats[2 * d + 1];
   if (!(sg > 0.0)) return;  // the whole workgroup: no events in a flat row
   const T* row = in + static_cast<int64_t>(d) * stride;
+  // 1 / (sigma sqrt(w)) for w = 1, 2, ..., 64: one lane each, shared through LDS
+  if (threadIdx.x < 7)
+    s_inv[threadIdx.x] =
+        static_cast<float>(1.0 / (sg * sqrt(static_cast<double>(1 << threadIdx.x))));
   constexpr int NL = (kStage + kThreads - 1) / kThreads;  // loads per lane
   if (t0 + kStage <= nout) {  // whole tile inside the row: all loads in flight at once
     T v[NL];
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
   }
   float inv[7];
 #pragma unroll
-  for (int k = 0; k < 7; k++) inv[k] = static_cast<float>(1.0 / (sg * sqrt(static_cast<double>(1 << k))));
+  for (int k = 0; k < 7; k++) inv[k] = s_inv[k];
   // every box of the tile ends inside the row: no per-box range test
   const bool inside = t0 + kTile + kHalo <= nout;
 #pragma unroll
