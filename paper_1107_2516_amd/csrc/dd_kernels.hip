@@ -27,11 +27,14 @@
 //                  VGPR-relative adds (generated asm, dd_window_asm.inc).
 //  2  BodyWin:     same, jump-table flavour of the asm step.
 //  3  BodyCopies:  u8 / f16; EPD shifted copies of each staged channel so
-//                  every DM reads aligned dwords; u8 sums in 16-bit SWAR
-//                  lanes with fast VOP2 instructions, f16 with v_fma_mix.
+//                  every DM reads aligned dwords; u8 sums two channels at a
+//                  time in 16-bit SWAR lanes, f16 with v_fma_mix.
 //  4  BodyWinX:    u8 / f16 through a register window: the staged rows are
 //                  expanded to one 32-bit word per sample (f16 -> FP32; u8 ->
 //                  two samples in 16-bit lanes, so one add sums two samples).
+//  5  BodyWin:     variant 1 with the window reloads scheduled on the host
+//                  (plan_wintab), so DMs that share a window switch only the
+//                  VGPR index.
 #include <cstring>
 #include <type_traits>
 
@@ -174,7 +177,7 @@ struct BodyLds {
   static constexpr int table_epd = 0;  // uses rel
 };
 
-// -------------------------------------------------------------- variants 1, 2
+// ----------------------------------------------------------- variants 1, 2, 5
 //
 // Register-window variant for FP32 input.  Lane l owns K *consecutive*
 // samples t0 + l*K + k, so the samples a lane needs for all DMs of its
@@ -188,6 +191,10 @@ struct BodyLds {
 // issued before stage s is computed.  The buffer descriptor of each channel
 // row bounds reads at nsamp samples, so samples past the end read as zero
 // (they only feed outputs t >= nout, which are not stored).
+//
+// SCHED (variant 5): the table holds host-scheduled window entries instead
+// of rel (plan_wintab), for the steps generated by gen_sched; the body is the
+// same.
 template <int DW, int K, int WMAX, int OCC_,
           void (*STEP)(float*, const int*, unsigned, const int32_t*, int*), bool SCHED = false>
 struct BodyWin {

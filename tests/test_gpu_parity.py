@@ -317,3 +317,20 @@ def test_unaligned_rows_fall_back(dtype):
     else:
         e, _ = scaled_error(y, x, tab)
         assert e <= FP_TOL
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8", "f16"])
+def test_autotune_then_execute(dtype):
+    """dd_autotune times its candidate shapes on this plan and size and
+    remembers the fastest; the next execute of that size class runs it and
+    still matches the oracle."""
+    g = np.random.default_rng(31 + len(dtype))
+    nchans, ndms, nsamp = 96, 70, 6000
+    tab = np.sort(rand_table(g, ndms, nchans, 300), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, dtype, nchans, nsamp)
+    tdt = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}[dtype]
+    tile, ms = plan.autotune(tdt, nsamp)
+    assert ms > 0
+    assert tile == plan.tile_for(tdt, nsamp)
+    _check(plan, x, tab, dtype)
