@@ -35,6 +35,7 @@ import json
 import math
 import os
 import sys
+import threading
 import time
 from concurrent.futures import ThreadPoolExecutor
 
@@ -587,6 +588,35 @@ def run_serve(dd, torch, args, nbeams=64):
     seq = [0] * nbeams
     stalls = {"n": 0}
 
+    # the client: one thread submits chunks, another collects results and
+    # releases their output memory as soon as they finish
+    done = {}
+    failed = []
+    stop = threading.Event()
+
+    def consume():
+        while not stop.is_set():
+            try:
+                rs = srv.poll(256)
+                for r in rs:
+                    if r.status != dd.DD_OK:
+                        failed.append(f"chunk {r.ticket} failed: {dd.status_str(r.status)}")
+                    done[r.ticket] = r
+                    srv.release(r.ticket)
+            except Exception as e:  # reported by the submitting thread
+                failed.append(repr(e))
+                return
+            if not rs:
+                time.sleep(2e-4)
+
+    consumer = threading.Thread(target=consume, daemon=True)
+    consumer.start()
+
+    def check():
+        if failed:
+            stop.set()
+            raise RuntimeError(failed[0])
+
     def submit(b, n):
         s = (phase[b] + pos[b]) % period
         while True:
@@ -596,27 +626,13 @@ def run_serve(dd, torch, args, nbeams=64):
                 seq[b] += 1
                 return tk
             stalls["n"] += 1
-            drain_some(block=True)
-
-    done = {}
-
-    def drain_some(block=False):
-        got = 0
-        while True:
-            rs = srv.poll(256)
-            for r in rs:
-                if r.status != dd.DD_OK:
-                    raise RuntimeError(f"chunk {r.ticket} failed: {dd.status_str(r.status)}")
-                done[r.ticket] = r
-                srv.release(r.ticket)
-            got += len(rs)
-            if got or not block:
-                return got
+            check()
             time.sleep(2e-4)
 
     def wait_all(tickets):
         while not all(t in done for t in tickets):
-            drain_some(block=True)
+            check()
+            time.sleep(2e-4)
 
     # warm-up: every beam needs max_shift samples of history before its first output
     log(f"serve: warming {nbeams} beams ({m} samples each)")
@@ -646,8 +662,7 @@ def run_serve(dd, torch, args, nbeams=64):
             now = time.monotonic()
             if now >= due:
                 break
-            if not drain_some():
-                time.sleep(min(5e-4, due - now))
+            time.sleep(min(5e-4, due - now))
         tk = submit(b, n)
         sched[tk] = (due, n)
     wait_all(list(sched))
@@ -669,6 +684,8 @@ def run_serve(dd, torch, args, nbeams=64):
     sat_wall = time.monotonic() - t0
     sat_samples = float(sum(lens))
     sat_lat = np.array([done[t].t_done - done[t].t_submit for t in sat])
+    stop.set()
+    consumer.join()
     srv.close()
 
     # the plain kernel at the serving shape (carry + one maximum chunk)
