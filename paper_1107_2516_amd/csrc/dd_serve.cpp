@@ -14,11 +14,15 @@
 // output fits (the memory rule of section 3, "Processable Samples").  Chunks
 // are staged in a pinned host pool at submit time.  A scheduler thread admits
 // chunks in arrival order (a beam's chunks strictly in order, other beams may
-// overtake a chunk that is waiting for memory), enqueues
-//   host->device copy, de-dispersion, carry move, completion event
-// on the beam's stream (beams are spread over the server's streams, so work
-// of different beams overlaps on the device while others are admitted), and
-// retires chunks as their events complete.
+// overtake a chunk that is waiting for memory) when the arena has room for
+// the chunk's device copy and its output, and enqueues
+//   host->device copy into the chunk's device staging (one copy stream, so
+//     copies run ahead in admission order while earlier chunks compute),
+//   then on the beam's stream: wait for that copy, place the chunk after the
+//     beam's carry, de-dispersion, carry move, completion event
+// (beams are spread over the server's streams, so work of different beams
+// overlaps on the device while others are admitted), and retires chunks as
+// their events complete.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -126,7 +130,10 @@ struct Chunk {
   int64_t t_first = 0, nout = 0, out_stride = 0;
   size_t out_off = 0, out_bytes = 0;
   void* d_out = nullptr;
-  hipEvent_t ev = nullptr;
+  size_t stage_off = 0, stage_bytes = 0;  // device copy of the chunk (arena)
+  unsigned char* d_stage = nullptr;
+  hipEvent_t ev = nullptr;       // all device work of the chunk done
+  hipEvent_t ev_copy = nullptr;  // host -> device copy done
   bool restart = false;
 };
 
@@ -154,6 +161,7 @@ struct dd_server {
   dd::RangeAlloc host_alloc;
   std::vector<dd::Beam> beams;
   std::vector<hipStream_t> streams;
+  hipStream_t copy_stream = nullptr;  // host -> device copies, in admission order
   std::vector<unsigned char*> temps;  // per stream, carry-move temporary
   std::vector<size_t> temp_size;
   std::deque<dd::Chunk*> pending;
@@ -179,11 +187,17 @@ dd_status enqueue_chunk(dd_server* s, Beam& b, Chunk* c, hipStream_t st) {
   const dd_plan* plan = b.plan;
   const int64_t nch = plan->nchans;
   const int64_t carry = b.S - b.E;  // samples at the front of the buffer
-  // host -> device: the chunk goes right after the carry
+  // host -> device on the copy stream, into the chunk's own device staging,
+  // so that it runs ahead while earlier chunks are de-dispersed; then, on the
+  // beam's stream, the chunk goes right after the carry
+  const size_t row = static_cast<size_t>(c->nsamp) * s->esize;
+  DD_HIP(hipMemcpyAsync(c->d_stage, s->pinned + c->h_off, row * static_cast<size_t>(nch),
+                        hipMemcpyHostToDevice, s->copy_stream));
+  DD_HIP(hipEventRecord(c->ev_copy, s->copy_stream));
+  DD_HIP(hipStreamWaitEvent(st, c->ev_copy, 0));
   DD_HIP(hipMemcpy2DAsync(b.d_buf + carry * s->esize, static_cast<size_t>(b.cap) * s->esize,
-                          s->pinned + c->h_off, static_cast<size_t>(c->nsamp) * s->esize,
-                          static_cast<size_t>(c->nsamp) * s->esize, static_cast<size_t>(nch),
-                          hipMemcpyHostToDevice, st));
+                          c->d_stage, row, row, static_cast<size_t>(nch), hipMemcpyDeviceToDevice,
+                          st));
   const int64_t S2 = b.S + c->nsamp;
   const int64_t E2 = std::max<int64_t>(0, S2 - plan->max_shift);
   c->t_first = b.E;
@@ -224,10 +238,17 @@ bool dd_server::admit_locked(dd::Chunk* c) {
   const int64_t S2 = b.S + c->nsamp;
   const int64_t E2 = std::max<int64_t>(0, S2 - b.plan->max_shift);
   const int64_t nout = E2 - b.E;
+  c->stage_bytes = static_cast<size_t>(c->nsamp) * b.plan->nchans * esize;
+  if (!dev_alloc.alloc(c->stage_bytes, &c->stage_off)) return false;  // wait for releases
+  c->d_stage = arena + c->stage_off;
   if (nout > 0) {
     c->out_stride = (nout + 63) & ~int64_t(63);
     c->out_bytes = static_cast<size_t>(b.plan->ndms) * c->out_stride * osize;
-    if (!dev_alloc.alloc(c->out_bytes, &c->out_off)) return false;  // wait for releases
+    if (!dev_alloc.alloc(c->out_bytes, &c->out_off)) {  // wait for releases
+      dev_alloc.release(c->stage_off, c->stage_bytes);
+      c->d_stage = nullptr;
+      return false;
+    }
     c->d_out = arena + c->out_off;
   }
   c->t_admit = dd::now_s();
@@ -253,6 +274,8 @@ void dd_server::retire_locked() {
     c->t_done = dd::now_s();
     host_alloc.release(c->h_off, c->h_bytes);
     c->h_bytes = 0;
+    dev_alloc.release(c->stage_off, c->stage_bytes);
+    c->d_stage = nullptr;
     done[c->ticket] = c;
     ready.push_back(c->ticket);
     inflight[i] = inflight.back();
@@ -285,6 +308,11 @@ void dd_server::run() {
         c->t_done = dd::now_s();
         host_alloc.release(c->h_off, c->h_bytes);
         c->h_bytes = 0;
+        // nothing of a failed enqueue may still read the staging: wait for it
+        (void)hipStreamSynchronize(copy_stream);
+        (void)hipStreamSynchronize(streams[beams[c->beam].stream]);
+        dev_alloc.release(c->stage_off, c->stage_bytes);
+        c->d_stage = nullptr;
         if (c->d_out) {
           dev_alloc.release(c->out_off, c->out_bytes);
           c->d_out = nullptr;
@@ -322,14 +350,17 @@ dd_server::~dd_server() {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(device);
   for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+  if (copy_stream) (void)hipStreamSynchronize(copy_stream);
   auto drop = [](dd::Chunk* c) {
     if (c->ev) (void)hipEventDestroy(c->ev);
+    if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
     delete c;
   };
   for (dd::Chunk* c : pending) drop(c);
   for (dd::Chunk* c : inflight) drop(c);
   for (auto& kv : done) drop(kv.second);
   for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+  if (copy_stream) (void)hipStreamDestroy(copy_stream);
   if (pinned) (void)hipHostFree(pinned);
   (void)hipSetDevice(cur);
 }
@@ -355,6 +386,7 @@ dd_status dd_serve_create(const dd_serve_config* cfg, void* d_arena, size_t aren
     DD_HIP(hipGetDevice(&s->device));
     DD_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->pinned), s->pinned_bytes, hipHostMallocDefault));
     s->host_alloc.reset(s->pinned_bytes);
+    DD_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
     for (int i = 0; i < cfg->nstreams; i++) {
       hipStream_t st = nullptr;
       DD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -428,7 +460,9 @@ dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64
     if (!s->host_alloc.alloc(bytes, &off)) return dd::set_error(DD_ERR_AGAIN, "staging pool full");
     std::unique_ptr<dd::Chunk> c(new dd::Chunk());
     hipError_t e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming);
     if (e != hipSuccess) {
+      if (c->ev) (void)hipEventDestroy(c->ev);
       s->host_alloc.release(off, bytes);
       return dd::hip_error(e, "hipEventCreate");
     }
@@ -494,6 +528,7 @@ dd_status dd_serve_release(dd_server* s, uint64_t ticket) {
   dd::Chunk* c = it->second;
   if (c->d_out) s->dev_alloc.release(c->out_off, c->out_bytes);
   if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
   delete c;
   s->done.erase(it);
   s->cv_work.notify_all();  // memory freed: admission may proceed

@@ -147,9 +147,10 @@ def test_admission_waits_for_memory_and_errors():
     plan = dd.Plan.from_delays(tab)
     m = int(tab.max())
     x = make_input(g, "u8", 24, 4 * 1024)
-    # arena: the beam buffer, one stream's carry temporary, room for one output
+    # arena: the beam buffer, one stream's carry temporary, room for one
+    # output and one chunk's device staging
     cap = (m + 1024 + 63) // 64 * 64
-    need = cap * 24 + ((m * 24 + 255) // 256) * 256 + 32 * 1024 * 4 + 4096
+    need = cap * 24 + ((m * 24 + 255) // 256) * 256 + 32 * 1024 * 4 + 1024 * 24 + 4096
     srv = dd.Server(_arena(need), torch.uint8, max_inflight=4, queue_capacity=3, nstreams=1)
     b = srv.add_beam(plan, 1024)
     with pytest.raises(dd.DedispError) as ei:
