@@ -188,3 +188,45 @@ def test_admission_waits_for_memory_and_errors():
     y = np.concatenate([results[t][1] for t in tickets if results[t][1] is not None], axis=1)
     assert np.array_equal(y.astype(np.int64), oracle.dedisperse(x, tab))
     srv.close()
+
+
+def test_full_shape_sampled_rows():
+    """The streaming workload's beam shape (2048 channels 120-180 MHz at
+    327.68 us, 4096 DMs step 0.125, max_shift 249888, chunks of 2^17 after
+    warm-up) through the server as the benchmark runs it: warm-up chunks emit
+    nothing, then chunks of 2^17, 2^14 and a ragged length; sampled DM rows of
+    every output chunk equal the oracle bit for bit, and the output times
+    continue exactly."""
+    import synth
+    band = synth.serve_band()
+    dms = synth.dm_grid(4096, 0.125)
+    plan = dd.Plan(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    tab = oracle.delay_table(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    m = int(tab.max())
+    assert m == plan.max_shift == 249888
+    max_chunk = 1 << 17
+    lens = [max_chunk, m - max_chunk, max_chunk, 1 << 14, 100003]
+    g = np.random.default_rng(2518)
+    x = g.integers(0, 256, size=(band.nchans, sum(lens)), dtype=np.uint8)
+    cap = (m + max_chunk + 63) // 64 * 64
+    arena = _arena(cap * band.nchans + m * band.nchans + 4 * max_chunk * 4096 * 4
+                   + 2 * max_chunk * band.nchans + (64 << 20))
+    srv = dd.Server(arena, torch.uint8, max_inflight=4, nstreams=2)
+    b = srv.add_beam(plan, max_chunk)
+    rows = [0, 1, 31, 32, 2047, 2048, 3001, 4095]
+    pos, nxt = 0, 0
+    for seq, n in enumerate(lens):
+        tk = srv.submit(b, x[:, pos:pos + n], seq)
+        assert tk is not None
+        got = _collect(srv, [tk])
+        t_first, y = got[tk]
+        pos += n
+        if pos <= m:
+            assert y is None  # warming up
+            continue
+        assert t_first == nxt and y.shape == (4096, pos - m - nxt)
+        ref = oracle.dedisperse(x, tab, rows=rows, t_begin=nxt, t_end=pos - m)
+        assert np.array_equal(y[rows].astype(np.int64), ref)
+        nxt = pos - m
+    assert nxt == sum(lens) - m
+    srv.close()
