@@ -422,12 +422,37 @@ def run_frontend(dd, torch, args, dm_row=333, t0=20000, width=8, amp=0.5):
     snr = boxcar_snr_peak(h_out[dm_row].numpy(), t0, width)
     ch_bytes = fe.nspec * fe.nsub * 8.0 + band.nchans * nt * 4.0
     ch_ach = ch_bytes / (ms[1] * 1e-3)
-    del d_v, d_p, d_out, h_v, h_out
+    # pipelined: two device voltage buffers; the next buffer's host->device
+    # copy runs on its own stream while this buffer is processed
+    cs = torch.cuda.Stream(dev)
+    d_vv = [d_v, torch.empty_like(d_v)]
+    freed = [torch.cuda.Event(), torch.cuda.Event()]
+    nbuf = 2 * steps
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for k in range(nbuf):
+        i = k % 2
+        if k >= 2:
+            cs.wait_event(freed[i])
+        with torch.cuda.stream(cs):
+            d_vv[i].copy_(h_v, non_blocking=True)
+            landed = torch.cuda.Event()
+            landed.record(cs)
+        stream.wait_event(landed)
+        dd.channelise(d_vv[i], fe.nfft, out=d_p, stream=stream)
+        plan.execute(d_p, out=d_out, stream=stream)
+        h_out.copy_(d_out, non_blocking=True)
+        freed[i].record(stream)
+    torch.cuda.synchronize()
+    pipe_ms = (time.perf_counter() - tp) * 1e3 / nbuf
+    del d_v, d_vv, d_p, d_out, h_v, h_out
     torch.cuda.empty_cache()
     return {"observation": "toy observation of the real-time test: 610 MHz centre, 20 MHz, "
                            "256 subbands at 12.8 us, 8 channels per subband, 500 DMs to 60, "
                            "buffers of 2^19 spectra (complex FP32 voltages)",
             "stage_ms": {n: float(m) for n, m in zip(names, ms)}, "total_ms": total,
+            "pipelined_ms_per_buffer": pipe_ms,
+            "pipelined_real_time_factor": pipe_ms / buffer_ms,
             "buffer_ms": buffer_ms, "real_time_factor": total / buffer_ms,
             "buffers_per_buffer_time": buffer_ms / total,
             "paper_c1060_total_ms": 5785.0, "tile": tile,
