@@ -62,9 +62,14 @@ void copy_rows(char* dst, const char* src, int64_t nrows, size_t row, size_t pit
     return;
   }
   std::vector<std::thread> th;
-  th.reserve(static_cast<size_t>(nt) - 1);
-  for (int64_t k = 1; k < nt; k++)
-    th.emplace_back(part, nrows * k / nt, nrows * (k + 1) / nt);
+  int64_t k = 1;
+  try {
+    th.reserve(static_cast<size_t>(nt) - 1);
+    for (; k < nt; k++) th.emplace_back(part, nrows * k / nt, nrows * (k + 1) / nt);
+  } catch (...) {
+    // no thread for parts k.. (resources exhausted): copied on this thread
+  }
+  for (int64_t q = k; q < nt; q++) part(nrows * q / nt, nrows * (q + 1) / nt);
   part(0, nrows / nt);
   for (auto& t : th) t.join();
 }
