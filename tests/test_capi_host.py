@@ -148,3 +148,73 @@ def test_channelise_argument_errors_before_any_gpu_work():
     assert L.dd_channelise(a, 64, 4, 4, 8, a, 7, None) == dd.DD_ERR_INVALID_ARG
     assert L.dd_channelise(a, 64, 4, 4, 3, a, 64, None) == dd.DD_ERR_INVALID_ARG
     assert L.dd_channelise(a, 64, 4, 4, 32, a, 64, None) == dd.DD_ERR_INVALID_ARG
+
+
+def test_serve_argument_errors_before_any_gpu_work():
+    L = dd.lib()
+    a = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    cfg = dd.ServeConfig(dd.DD_U8, dd.DD_I32, 4, 16, 2, 0)
+    assert L.dd_serve_create(None, a, 1 << 20, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_serve_create(ctypes.byref(cfg), None, 1 << 20, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+    bad = dd.ServeConfig(dd.DD_U8, dd.DD_F32, 4, 16, 2, 0)
+    assert L.dd_serve_create(ctypes.byref(bad), a, 1 << 20, ctypes.byref(h)) == dd.DD_ERR_DTYPE
+    for mi, qc, ns in [(0, 16, 2), (4, 0, 2), (4, 16, 0), (4, 16, 17)]:
+        c = dd.ServeConfig(dd.DD_U8, dd.DD_I32, mi, qc, ns, 0)
+        assert L.dd_serve_create(ctypes.byref(c), a, 1 << 20, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+    b = ctypes.c_int32()
+    t = ctypes.c_uint64()
+    n = ctypes.c_int32()
+    assert L.dd_serve_add_beam(None, a, 10, ctypes.byref(b)) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_serve_submit(None, 0, a, 10, 10, 0, ctypes.byref(t)) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_serve_poll(None, None, 0, ctypes.byref(n)) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_serve_release(None, 1) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_serve_drain(None) == dd.DD_ERR_INVALID_ARG
+    assert L.dd_serve_stats(None, None, None, None, None) == dd.DD_ERR_INVALID_ARG
+
+
+def test_batch_argument_errors_before_any_gpu_work():
+    L = dd.lib()
+    h = ctypes.c_void_p()
+    plan = dd.Plan.from_delays(np.array([[0, 1, 2], [0, 2, 4]], dtype=np.int32))
+    assert L.dd_batch_create(None, 0, dd.DD_U8, dd.DD_I32, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+    items = (dd.BatchItem * 1)()
+    items[0] = dd.BatchItem(plan.handle.value, 0x1000, 100, 100, 0x2000, 100)
+    assert L.dd_batch_create(items, 1, dd.DD_U8, dd.DD_F32, ctypes.byref(h)) == dd.DD_ERR_DTYPE
+    items[0] = dd.BatchItem(plan.handle.value, 0x1000, 4, 4, 0x2000, 100)  # nsamp <= max_shift
+    assert L.dd_batch_create(items, 1, dd.DD_U8, dd.DD_I32, ctypes.byref(h)) == dd.DD_ERR_NSAMP
+    items[0] = dd.BatchItem(plan.handle.value, 0x1000, 100, 50, 0x2000, 100)  # stride < nsamp
+    assert L.dd_batch_create(items, 1, dd.DD_U8, dd.DD_I32, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+    items[0] = dd.BatchItem(None, 0x1000, 100, 100, 0x2000, 100)
+    assert L.dd_batch_create(items, 1, dd.DD_U8, dd.DD_I32, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("nsub", [1, 8, 32])
+def test_subband_plan_dms_match_oracle(nsub):
+    """A subband plan is built on the host: its DM list per pass equals the
+    oracle's fine DMs of the paper's Table 1 passes, and its per-pass output
+    lengths follow the binned maximum shifts."""
+    passes = [(0.0, 53.46, 0.03, 0.66, 1), (53.46, 88.26, 0.05, 1.2, 2),
+              (88.26, 150.66, 0.10, 2.4, 4)]
+    sp = dd.SubbandPlan(1024, 1510.0, 296.0 / 1024, 64e-6, nsub, passes)
+    dms, pass_of = sp.dms()
+    want = np.concatenate([oracle.subband_pass_dms(lo, hi, d, s)[0] for lo, hi, d, s, _ in passes])
+    assert sp.ndms == want.size
+    np.testing.assert_array_equal(dms, want)
+    counts = [oracle.subband_pass_dms(lo, hi, d, s)[0].size for lo, hi, d, s, _ in passes]
+    np.testing.assert_array_equal(pass_of, np.repeat(np.arange(3), counts))
+    nout, ws = sp.sizes(1 << 18)
+    assert ws > 0 and all(0 < n <= (1 << 18) // b for n, (_, _, _, _, b) in zip(nout, passes))
+    sp.close()
+
+
+@pytest.mark.parametrize("bad", [
+    [(0.0, 10.0, 0.0, 1.0, 1)],        # ddm = 0
+    [(5.0, 1.0, 0.1, 1.0, 1)],         # dm_hi < dm_lo
+    [(0.0, 10.0, 0.1, 1.0, 0)],        # bin 0
+    [(0.0, 10.0, 0.1, 1.0, 1), (5.0, 20.0, 0.1, 1.0, 1)],  # overlapping passes
+])
+def test_subband_plan_rejects_bad_passes(bad):
+    with pytest.raises(dd.DedispError) as ei:
+        dd.SubbandPlan(64, 432.0, 0.5, 64e-6, 8, bad)
+    assert ei.value.status == dd.DD_ERR_INVALID_ARG
