@@ -156,6 +156,12 @@ dd_status dd_batch_update(dd_batch* batch, const dd_batch_item* items, int32_t n
 /* Enqueue the whole batch on `stream` (graph replay). */
 dd_status dd_batch_launch(dd_batch* batch, void* stream);
 
+/* Use tile shape *cfg for every beam of the batch (its graph is re-recorded
+ * on the next launch).  DD_ERR_NOT_IMPLEMENTED for a shape no kernel has,
+ * DD_ERR_TOO_LARGE when some beam does not fit it (the batch keeps its
+ * previous shape then). */
+dd_status dd_batch_set_tile(dd_batch* batch, const dd_tile_config* cfg);
+
 /* Work items (beam, DM tile, time tile), persistent grid size and the tile
  * shape of a batch; any output pointer may be NULL. */
 dd_status dd_batch_info(const dd_batch* batch, int32_t* work_items, int32_t* grid,

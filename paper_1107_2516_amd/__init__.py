@@ -95,6 +95,7 @@ _SIGS = {
     "dd_batch_destroy": [_P],
     "dd_batch_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(TileConfig)],
     "dd_batch_autotune": [_P, _P, ctypes.POINTER(TileConfig), ctypes.POINTER(ctypes.c_float)],
+    "dd_batch_set_tile": [_P, ctypes.POINTER(TileConfig)],
     "dd_execute_tiled": [_P, _P, ctypes.c_int, _I64, _I64, _P, ctypes.c_int, _I64,
                          ctypes.POINTER(TileConfig), _P],
     "dd_autotune": [_P, ctypes.c_int, _I64, _P, ctypes.POINTER(TileConfig), ctypes.POINTER(ctypes.c_float)],
@@ -348,6 +349,12 @@ class Batch:
         n, g, cfg = _I32(), _I32(), TileConfig()
         _check(lib().dd_batch_info(self._h, ctypes.byref(n), ctypes.byref(g), ctypes.byref(cfg)))
         return {"work_items": n.value, "grid": g.value, "tile": cfg.as_dict()}
+
+    def set_tile(self, tile):
+        """Force one tile shape (a dict like info()["tile"]) for every beam."""
+        cfg = TileConfig(int(tile["variant"]), int(tile["dms_per_wave"]), int(tile["waves"]),
+                         int(tile["tsamp_per_lane"]), int(tile["chans_per_stage"]))
+        _check(lib().dd_batch_set_tile(self._h, ctypes.byref(cfg)))
 
     def autotune(self, stream=None):
         cfg, ms = TileConfig(), ctypes.c_float()

@@ -247,6 +247,25 @@ dd_status dd_batch_launch(dd_batch* b, void* stream) {
   }
 }
 
+dd_status dd_batch_set_tile(dd_batch* b, const dd_tile_config* cfg) {
+  try {
+    if (!b || !cfg) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+    dd::TileShape s;
+    s.variant = cfg->variant;
+    s.dms_per_wave = cfg->dms_per_wave;
+    s.waves = cfg->waves;
+    s.tsamp_per_lane = cfg->tsamp_per_lane;
+    s.chans_per_stage = cfg->chans_per_stage;
+    if (!dd::shape_supported(s, b->in_t))
+      return dd::set_error(DD_ERR_NOT_IMPLEMENTED, "no kernel for this tile shape / type");
+    return dd::batch_set_shape(b, s);
+  } catch (const std::bad_alloc&) {
+    return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
+}
+
 dd_status dd_batch_info(const dd_batch* b, int32_t* work_items, int32_t* grid,
                         dd_tile_config* cfg) {
   if (!b) return dd::set_error(DD_ERR_INVALID_ARG, "batch is NULL");

@@ -187,6 +187,8 @@ def test_batch_argument_errors_before_any_gpu_work():
     assert L.dd_batch_create(items, 1, dd.DD_U8, dd.DD_I32, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
     items[0] = dd.BatchItem(None, 0x1000, 100, 100, 0x2000, 100)
     assert L.dd_batch_create(items, 1, dd.DD_U8, dd.DD_I32, ctypes.byref(h)) == dd.DD_ERR_INVALID_ARG
+    cfg = dd.TileConfig(3, 8, 4, 16, 8)
+    assert L.dd_batch_set_tile(None, ctypes.byref(cfg)) == dd.DD_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("nsub", [1, 8, 32])

@@ -132,3 +132,36 @@ def test_batch_workload_subset_sampled_rows():
         rows = [0, p.ndms // 3, p.ndms - 1]
         ref = oracle.dedisperse(x, tab, rows=rows)
         assert np.array_equal(o[rows].cpu().numpy().astype(np.int64), ref)
+
+
+def test_batch_set_tile_every_u8_shape():
+    """Forcing each 8-bit tile shape on one batch keeps every beam's output
+    equal to the oracle; a shape no kernel has is refused and the batch keeps
+    working with its previous shape."""
+    beams = _beams("u8", 21)
+    plans = [dd.Plan.from_delays(t) for t, _ in beams]
+    xs = []
+    for _, x in beams:  # rows pitched to 64 bytes, as the aligned-copies kernels need
+        buf = torch.zeros((x.shape[0], (x.shape[1] + 63) // 64 * 64), dtype=torch.uint8,
+                          device="cuda")
+        buf[:, :x.shape[1]].copy_(torch.from_numpy(x))
+        xs.append(buf[:, :x.shape[1]])
+    b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    for tile in [dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=8),
+                 dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=4),
+                 dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=8),
+                 dict(variant=0, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)]:
+        b.set_tile(tile)
+        assert b.info()["tile"] == tile
+        outs = b.launch()
+        torch.cuda.synchronize()
+        for (tab, x), o in zip(beams, outs):
+            _check(o.cpu().numpy(), x, tab, "u8")
+    with pytest.raises(dd.DedispError) as ei:
+        b.set_tile(dict(variant=3, dms_per_wave=5, waves=4, tsamp_per_lane=16, chans_per_stage=8))
+    assert ei.value.status == dd.DD_ERR_NOT_IMPLEMENTED
+    outs = b.launch()
+    torch.cuda.synchronize()
+    for (tab, x), o in zip(beams, outs):
+        _check(o.cpu().numpy(), x, tab, "u8")
+
