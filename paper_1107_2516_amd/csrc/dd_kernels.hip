@@ -10,8 +10,9 @@
 // [t0 + base_c, t0 + base_c + slot), base_c being the smallest shift of
 // channel c in the tile; every DM of the tile then reads its shifted samples
 // from that window, so one L2/HBM read of a sample feeds TD DMs.  The
-// per-(tile, channel, DM) shift differences come from host tables read with
-// scalar loads.
+// per-(tile, channel, DM) shift differences come from host tables, read with
+// scalar loads one channel ahead (register-window variants) or staged in LDS
+// beside the data (aligned-copies variant).
 //
 // Each variant is a per-tile device body.  It runs either from a plain grid
 // (one workgroup per tile, XCD-aware numbering: block b runs on XCD b mod 8,
