@@ -334,3 +334,45 @@ def test_autotune_then_execute(dtype):
     assert ms > 0
     assert tile == plan.tile_for(tdt, nsamp)
     _check(plan, x, tab, dtype)
+
+
+def test_one_plan_from_many_threads_and_streams():
+    """A fresh plan used by four host threads at once, each on its own stream
+    and with its own tile shape: the lazily built device tables are created
+    once under the plan's lock and every result matches the oracle."""
+    import threading
+    g = np.random.default_rng(77)
+    nchans, ndms, nsamp = 64, 70, 5000
+    tab = np.sort(rand_table(g, ndms, nchans, 300), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    x = make_input(g, "f32", nchans, nsamp)
+    xt = torch.from_numpy(x).cuda()
+    tiles = [dict(variant=5, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+             dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+             dict(variant=5, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
+             dict(variant=0, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)]
+    outs, errs = [None] * 4, []
+    barrier = threading.Barrier(4)
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                barrier.wait()
+                o = plan.execute_tiled(xt, tiles[i], stream=s)
+                s.synchronize()
+                outs[i] = o.cpu().numpy()
+        except Exception as e:  # reported below
+            errs.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for o in outs:
+        e, _ = scaled_error(o, x, tab)
+        assert e <= FP_TOL, e
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])  # every variant sums the channels in the same order
