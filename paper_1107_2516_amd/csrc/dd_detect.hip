@@ -94,6 +94,9 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
   const double sg = stats[2 * d + 1];
   if (!(sg > 0.0)) return;  // the whole workgroup: no events in a flat row
   const T* row = in + static_cast<int64_t>(d) * stride;
+  // samples are centred in FP32: x - mu rounded once more than in FP64, far
+  // below the resolution of the S/N threshold test
+  const float muf = static_cast<float>(mu);
   // 1 / (sigma sqrt(w)) for w = 1, 2, ..., 64: one lane each, shared through LDS
   if (threadIdx.x < 7)
     s_inv[threadIdx.x] =
@@ -109,12 +112,12 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
 #pragma unroll
     for (int u = 0; u < NL; u++) {
       const int i = threadIdx.x + u * kThreads;
-      if (i < kStage) y[padded(i)] = static_cast<float>(static_cast<double>(v[u]) - mu);
+      if (i < kStage) y[padded(i)] = static_cast<float>(v[u]) - muf;
     }
   } else {
     for (int i = threadIdx.x; i < kStage; i += kThreads) {
       const int64_t t = t0 + i;
-      y[padded(i)] = t < nout ? static_cast<float>(static_cast<double>(row[t]) - mu) : 0.f;
+      y[padded(i)] = t < nout ? static_cast<float>(row[t]) - muf : 0.f;
     }
   }
   __syncthreads();
