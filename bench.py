@@ -790,8 +790,8 @@ def base_line(args, metric_value, ms_per_step, dtype, config, rl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not launched"}))
+        print(json.dumps({"error": "runs on one GPU only: sharding over several GPUs is "
+                                   "designed but not launched (use --gpus 1)"}))
         sys.exit(2)
     import torch
     import paper_1107_2516_amd as dd
