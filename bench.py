@@ -210,6 +210,19 @@ def run_single(dd, torch, plan, w, xh, dt, args):
     unit = "TOP/s" if dt == "u8" else "TFLOP/s"
     rl = roofline(adds, float(plan.nchans) * nsamp * xh.dtype.itemsize,
                   float(plan.ndms) * nout * 4, kms, unit)
+    # spread of single launches (HIP events around each one), after the timed run
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        plan.execute(xin, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    each = np.array([a.elapsed_time(b) for a, b in ev])
+    rl["kernel_ms_p10_p50_p90"] = [float(v) for v in np.percentile(each, [10, 50, 90])]
+    # the same adds against 64 adds per CU per clock (39.3e12/s), a peak that
+    # plain v_add_f32 was measured to exceed on this chip
+    rl["frac_vs_39T_adds"] = adds / (kms * 1e-3) / (PEAK_ADD_PER_S / 2)
     return {"kernel_ms": kms, "ms_per_step": wall_ms, "value": plan.ndms * nout / (wall_ms * 1e-3),
             "roofline": rl, "tile": plan.tile_for(xin.dtype, nsamp),
             "real_time_factor": (kms * 1e-3) / (nout * w.band.t_samp)}, out
@@ -262,7 +275,16 @@ def cpu_baseline(w, xs, outs, budget_s):
     res = {"value": nrows * nout / dt, "unit": "DM-trial samples/s", "cores": threads,
            "kind": "oracle",
            "sample": f"{nrows} of {ndms} DM rows x {nout} output samples x {b.nchans} channels "
-                     f"({dt:.1f} s on {threads} threads)"}
+                     f"({dt:.1f} s on {threads} threads)",
+           "cpu_model": cpu_model()}
+    # one core, as the paper's CPU baseline: a few rows
+    one = rows[:: max(1, nrows // 4)][:4]
+    t1 = time.perf_counter()
+    oracle.dedisperse(x, tab, rows=one, nthreads=1)
+    d1 = time.perf_counter() - t1
+    res["single_core"] = {"value": len(one) * nout / d1, "unit": "DM-trial samples/s",
+                          "sample": f"{len(one)} DM rows x {nout} output samples on 1 thread "
+                                    f"({d1:.1f} s)"}
     # accuracy of each GPU result on (up to) 16 of the sampled rows
     sub = np.unique(np.linspace(0, nrows - 1, min(nrows, 16)).astype(np.int64))
     r_rows = rows[sub]
@@ -286,6 +308,17 @@ def cpu_baseline(w, xs, outs, budget_s):
                           "rel_err_vs_fp64_f32_input": normwise(y, ref_rows)}
     res["accuracy"] = acc
     return res
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def torch_index(rows):
@@ -870,6 +903,8 @@ def main():
         log("cpu baseline: timing the oracle")
         line["cpu_baseline"] = cpu_baseline(w, xs, outs, args.cpu_seconds)
         line["cpu_baseline"]["gpu_over_cpu"] = line["value"] / line["cpu_baseline"]["value"]
+        sc = line["cpu_baseline"]["single_core"]
+        sc["gpu_over_single_core"] = line["value"] / sc["value"]
     del outs, main_out
     torch.cuda.empty_cache()
     if extras:
