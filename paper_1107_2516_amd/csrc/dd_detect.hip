@@ -10,8 +10,12 @@
 //     stages y = x - mu (FP32) plus a 64-sample halo in LDS (four padding
 //     words every 16 so that lanes read their runs with conflict-free 16-byte
 //     reads), and each lane turns its 16 samples + halo into register prefix
-//     sums, from which every box of every width is one subtraction.  Events
-//     are appended with one 64-bit atomic per wavefront and sample slot.
+//     sums, from which every box of every width is one subtraction.  A box
+//     is first compared with a threshold lowered by a relative 1e-5 (no
+//     multiply, no max); only a wavefront where some lane passes that test
+//     computes the exact S/N, so the events are those of the exact test
+//     alone.  Events are appended with one 64-bit atomic per wavefront and
+//     sample slot.
 #include "dd_internal.h"
 
 namespace dd {
@@ -88,6 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
                                                      unsigned long long* __restrict__ count) {
   __shared__ __align__(16) float y[kLds];
   __shared__ float s_inv[8];
+  __shared__ float s_thr[8];
   const int d = blockIdx.y;
   const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTile;
   const double mu = stats[2 * d];
@@ -98,9 +103,22 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
   // below the resolution of the S/N threshold test
   const float muf = static_cast<float>(mu);
   // 1 / (sigma sqrt(w)) for w = 1, 2, ..., 64: one lane each, shared through LDS
-  if (threadIdx.x < 7)
-    s_inv[threadIdx.x] =
+  // and the prefilter thresholds: every box whose exact S/N test passes
+  // (box * inv rounded to FP32 >= nsigma) is >= nsigma / inv less a relative
+  // 1e-5, far more than the two roundings involved; where that bound is not
+  // finite the prefilter passes every box; widths above the limit get a NaN
+  // threshold, which no box passes
+  if (threadIdx.x < 7) {
+    const float inv =
         static_cast<float>(1.0 / (sg * sqrt(static_cast<double>(1 << threadIdx.x))));
+    s_inv[threadIdx.x] = inv;
+    double tl = static_cast<double>(nsigma) / static_cast<double>(inv);
+    tl -= fabs(tl) * 1e-5 + 1e-30;
+    const float tf = static_cast<float>(tl);
+    s_thr[threadIdx.x] = static_cast<int>(threadIdx.x) > kmax        ? __builtin_nanf("")
+                         : isfinite(tl) && isfinite(tf) ? tf
+                                                        : -INFINITY;
+  }
   constexpr int NL = (kStage + kThreads - 1) / kThreads;  // loads per lane
   if (t0 + kStage <= nout) {  // whole tile inside the row: all loads in flight at once
     T v[NL];
@@ -145,14 +163,27 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
       }
     }
   }
-  float inv[7];
+  float inv[7], thr[7];
 #pragma unroll
-  for (int k = 0; k < 7; k++) inv[k] = s_inv[k];
+  for (int k = 0; k < 7; k++) {
+    inv[k] = s_inv[k];
+    thr[k] = s_thr[k];
+  }
   // every box of the tile ends inside the row: no per-box range test
   const bool inside = t0 + kTile + kHalo <= nout;
 #pragma unroll
   for (int i = 0; i < kRun; i++) {
     const int64_t t = t0 + base + i;
+    bool pre = false;
+    if (inside) {
+#pragma unroll
+      for (int k = 0; k < 7; k++) pre |= p[i + (1 << k)] - p[i] >= thr[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 7; k++)
+        if (t + (1 << k) <= nout) pre |= p[i + (1 << k)] - p[i] >= thr[k];
+    }
+    if (__ballot(pre) == 0ull) continue;  // no lane of the wavefront can hold an event here
     float m = -INFINITY;  // the best S/N of the sample (max over widths)
     if (inside) {
 #pragma unroll
@@ -163,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
       for (int k = 0; k < 7; k++)
         if (k <= kmax && t + (1 << k) <= nout) m = fmaxf(m, (p[i + (1 << k)] - p[i]) * inv[k]);
     }
-    const bool hit = m >= nsigma;
+    const bool hit = t < nout && m >= nsigma;  // lanes past the row end hold no sample
     float best = m;
     int bw = 0;
     if (hit) {  // rare: the smallest width that reaches the maximum
