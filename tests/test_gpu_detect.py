@@ -120,3 +120,18 @@ def test_detect_after_dedispersion():
     expect = 768.0 / (np.sqrt(64.0 + 4 * 192.0 ** 2 / nout) * 2.0)
     assert abs(float(top["snr"]) - expect) < 3.0
     _check(ev, y.cpu().numpy(), 8.0, 6)
+
+
+def test_every_sample_is_an_event_below_any_threshold():
+    """nsigma = -inf: each sample of each row (ragged last tile: 5000 = 4096 +
+    904) is one event, and no event lies past the row end.  The S/N and
+    width of each agree with the oracle."""
+    g = np.random.default_rng(11)
+    x = g.standard_normal((3, 5000)).astype(np.float32)
+    ev, _, total = dd.detect(torch.from_numpy(x).cuda(), -np.inf, 6)
+    assert total == len(ev) == x.size
+    assert ev["t"].max() == x.shape[1] - 1 and ev["t"].min() == 0
+    ref = oracle.detect_boxcar(x, -np.inf, 6)
+    assert len(ref) == x.size
+    assert np.array_equal(ev["dm_row"], ref["dm_row"]) and np.array_equal(ev["t"], ref["t"])
+    assert np.allclose(ev["snr"], ref["snr"], rtol=EPS, atol=EPS)
