@@ -461,15 +461,19 @@ dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64
     if (static_cast<int32_t>(s->pending.size()) >= s->cfg.queue_capacity)
       return dd::set_error(DD_ERR_AGAIN, "submit queue full");
     const size_t bytes = static_cast<size_t>(nsamp) * b.plan->nchans * s->esize;
-    size_t off = 0;
-    if (!s->host_alloc.alloc(bytes, &off)) return dd::set_error(DD_ERR_AGAIN, "staging pool full");
+    // everything that can fail comes before the staging range is taken
     std::unique_ptr<dd::Chunk> c(new dd::Chunk());
     hipError_t e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming);
     if (e != hipSuccess) {
       if (c->ev) (void)hipEventDestroy(c->ev);
-      s->host_alloc.release(off, bytes);
       return dd::hip_error(e, "hipEventCreate");
+    }
+    size_t off = 0;
+    if (!s->host_alloc.alloc(bytes, &off)) {
+      (void)hipEventDestroy(c->ev);
+      (void)hipEventDestroy(c->ev_copy);
+      return dd::set_error(DD_ERR_AGAIN, "staging pool full");
     }
     c->ticket = s->next_ticket++;
     c->beam = beam;
@@ -487,8 +491,20 @@ dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64
     dd::copy_rows(reinterpret_cast<char*>(s->pinned + off), static_cast<const char*>(h_chunk), nchans,
                   static_cast<size_t>(nsamp) * s->esize, static_cast<size_t>(in_stride) * s->esize);
     lk.lock();
-    *ticket = c->ticket;
-    s->pending.push_back(c.release());
+    try {
+      s->pending.push_back(c.get());
+    } catch (const std::bad_alloc&) {
+      // the chunk is dropped: its beam restarts at the next chunk unless this
+      // seq is submitted again (the beams vector may have grown meanwhile)
+      dd::Beam& bb = s->beams[beam];
+      bb.pending--;
+      bb.next_seq = seq;
+      s->host_alloc.release(off, bytes);
+      (void)hipEventDestroy(c->ev);
+      (void)hipEventDestroy(c->ev_copy);
+      return dd::set_error(DD_ERR_OOM, "host allocation failed");
+    }
+    *ticket = c.release()->ticket;
     s->cv_work.notify_all();
     return DD_OK;
   } catch (const std::bad_alloc&) {
