@@ -89,11 +89,6 @@ def max_threads() -> int:
     return int(_load().orc_max_threads())
 
 
-def channel_freqs(nchans: int, f_top: float, df: float) -> np.ndarray:
-    """f_c = f_top - c*df, channel 0 at the top (section 4, Table 2 parameters)."""
-    return np.array([f_top - c * df for c in range(nchans)], dtype=np.float64)
-
-
 def delay_table(nchans: int, f_top: float, df: float, t_samp: float, dms) -> np.ndarray:
     """Integer shifts [ndms, nchans] in samples (section 3, "Shifts").
 

@@ -220,3 +220,12 @@ def test_subband_plan_rejects_bad_passes(bad):
     with pytest.raises(dd.DedispError) as ei:
         dd.SubbandPlan(64, 432.0, 0.5, 64e-6, 8, bad)
     assert ei.value.status == dd.DD_ERR_INVALID_ARG
+
+
+def test_exact_half_sample_tie_rounds_like_the_oracle():
+    """4150 * (1 - 1/4) * DM is an exact .5 for odd DM: the host plan must take
+    the same side of the tie as the oracle (away from zero)."""
+    dms = [1.0, 3.0, 5.0]
+    p = dd.Plan(2, 2.0, 1.0, 1.0, dms)
+    assert p.delay_table().astype(np.int64).tolist() == [[0, 3113], [0, 9338], [0, 15563]]
+    assert np.array_equal(p.delay_table(), oracle.delay_table(2, 2.0, 1.0, 1.0, dms))

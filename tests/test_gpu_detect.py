@@ -135,3 +135,19 @@ def test_every_sample_is_an_event_below_any_threshold():
     assert len(ref) == x.size
     assert np.array_equal(ev["dm_row"], ref["dm_row"]) and np.array_equal(ev["t"], ref["t"])
     assert np.allclose(ev["snr"], ref["snr"], rtol=EPS, atol=EPS)
+
+
+def test_exact_tie_takes_the_smallest_width():
+    """A zero-mean row of small integers where the width-4 box at t = 10 sums
+    to twice the single sample: S/N 8/sigma for both widths (sigma = 1.5, the
+    FP32 factors 1/sigma and 1/(2 sigma) differ by exactly 2), so the tie is
+    exact in FP32 too and the smallest width must win, as in the oracle."""
+    r = np.zeros((1, 64), dtype=np.float32)
+    r[0, 10], r[0, 13] = 8.0, 8.0
+    r[0, 14:30] = -1.0
+    ev, stats, _ = dd.detect(torch.from_numpy(r).cuda(), 1.0, 6)
+    assert stats[0, 1].item() == 1.5
+    e = ev[ev["t"] == 10][0]
+    assert int(e["width"]) == 1 and abs(float(e["snr"]) - 8.0 / 1.5) < 1e-6
+    ref = oracle.detect_boxcar(r.astype(np.float64), 1.0, 6)
+    assert int(ref[ref["t"] == 10][0]["width"]) == 1

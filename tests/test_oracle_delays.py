@@ -155,3 +155,12 @@ def test_half_decoding_all_patterns():
     assert np.array_equal(got[fin], r[fin])
     assert np.array_equal(np.isnan(got), np.isnan(r))
     assert np.array_equal(np.isinf(got), np.isinf(r))
+
+
+def test_exact_half_sample_rounds_away_from_zero():
+    """With f_top = 2, f_c = 1 (df = 1), t_samp = 1: t_chan = 4150 * (1 - 1/4)
+    = 3112.5 exactly in binary floating point, so DM 1 lands on a true tie
+    between 3112 and 3113.  The reading used (ties away from zero) gives 3113;
+    DM 3 (9337.5) and DM 5 (15562.5) are ties as well."""
+    t = oracle.delay_table(2, 2.0, 1.0, 1.0, [1.0, 3.0, 5.0])
+    assert t.tolist() == [[0, 3113], [0, 9338], [0, 15563]]

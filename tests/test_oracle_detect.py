@@ -99,3 +99,28 @@ def test_boxes_stop_at_the_row_end():
     last = ev[ev["t"] >= 61]
     assert len(last) == 3
     assert all(t + w <= 64 for t, w in zip(last["t"], last["width"]))
+
+
+def _tie_row():
+    """A zero-mean row of small integers (so mu, every box sum and sigma*2 are
+    exact) where the box of width 4 at t = 10 sums to twice the single sample
+    there: S/N(w=4) = 16 / (2 sigma) = 8 / sigma = S/N(w=1), an exact tie,
+    and every other width at t = 10 scores lower."""
+    r = np.zeros(64)
+    r[10], r[13] = 8.0, 8.0
+    r[14:30] = -1.0
+    assert r.sum() == 0.0
+    return r
+
+
+def test_exact_tie_takes_the_smallest_width():
+    r = _tie_row()
+    sigma = r.std()
+    ev = oracle.detect_boxcar(r[None, :], 1.0, 6)
+    e = ev[ev["t"] == 10][0]
+    assert e["snr"] == 8.0 / sigma == 16.0 / (sigma * 2.0)
+    assert e["width"] == 1
+    # a sample whose best S/N equals the threshold exactly is an event (>=)
+    at = oracle.detect_boxcar(r[None, :], float(e["snr"]), 6)
+    assert 10 in at["t"] and 13 in at["t"]
+    assert at["snr"].min() == e["snr"]
