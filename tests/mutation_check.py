@@ -37,6 +37,19 @@ MUTS = [
     ("P9 one fine DM fewer", P, "nfine = int(math.ceil((dm_hi - dm_lo) / ddm - 1e-9))", "nfine = int(math.ceil((dm_hi - dm_lo) / ddm - 1e-9)) - 1"),
     ("P10 delay rounding half-even", C, "(int64_t)llround(x)", "(int64_t)nearbyint(x)"),
     ("C9 t_begin ignored", C, "in + c * stride + t_begin + dl[c]", "in + c * stride + dl[c]"),
+    ("C10 u8 read as signed", C, "#define CONV_U8(x) ((int64_t)(x))", "#define CONV_U8(x) ((int64_t)(int8_t)(x))"),
+    ("C11 f32 summed in float", C, "DEFINE_DEDISP(orc_dedisperse_f32, float, double, CONV_F32)",
+     "DEFINE_DEDISP(orc_dedisperse_f32_unused, float, double, CONV_F32)\n"
+     "static int orc_f32_float_acc(const float* in, int64_t nchans, int64_t nsamp, int64_t stride, const int64_t* delays,"
+     " int32_t ndms, const int32_t* rows, int32_t nrows, int64_t t_begin, int64_t t_end, double* out, int32_t nthreads) {"
+     " int rc = orc_dedisperse_f32_unused(in, nchans, nsamp, stride, delays, ndms, rows, nrows, t_begin, t_end, out, nthreads);"
+     " if (rc != ORC_OK) return rc; int64_t n = t_end - t_begin;"
+     " for (int32_t i = 0; i < nrows; i++) { const int64_t* dl = delays + (int64_t)rows[i] * nchans;"
+     " for (int64_t t = 0; t < n; t++) { float a = 0.f; for (int64_t c = 0; c < nchans; c++) a += in[c * stride + t_begin + t + dl[c]];"
+     " out[(int64_t)i * n + t] = a; } } return ORC_OK; }\n"
+     "int orc_dedisperse_f32(const float* in, int64_t nchans, int64_t nsamp, int64_t stride, const int64_t* delays,"
+     " int32_t ndms, const int32_t* rows, int32_t nrows, int64_t t_begin, int64_t t_end, double* out, int32_t nthreads) {"
+     " return orc_f32_float_acc(in, nchans, nsamp, stride, delays, ndms, rows, nrows, t_begin, t_end, out, nthreads); }"),
     ("P11 threshold strict", P, "t = np.nonzero(best >= nsigma)[0]", "t = np.nonzero(best > nsigma)[0]"),
     ("P12 corner flip ignored", P, "    if flip:\n        x = x[:, ::-1]", "    if False:\n        x = x[:, ::-1]"),
 ]
