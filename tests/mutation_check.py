@@ -50,6 +50,13 @@ MUTS = [
      "int orc_dedisperse_f32(const float* in, int64_t nchans, int64_t nsamp, int64_t stride, const int64_t* delays,"
      " int32_t ndms, const int32_t* rows, int32_t nrows, int64_t t_begin, int64_t t_end, double* out, int32_t nthreads) {"
      " return orc_f32_float_acc(in, nchans, nsamp, stride, delays, ndms, rows, nrows, t_begin, t_end, out, nthreads); }"),
+    ("P13 nominal DM at range start", P, "nominal = dm_lo + (np.arange(nnom, dtype=np.float64) + 0.5) * dsub",
+     "nominal = dm_lo + np.arange(nnom, dtype=np.float64) * dsub"),
+    ("P14 subband top off by one", P, "t1 = dn[:, c0:c0 + cps] - dn[:, [c0]]", "t1 = dn[:, c0:c0 + cps] - dn[:, [min(c0 + 1, nchans - 1)]] + 1"),
+    ("P15 stage 2 at bottom channel", P, "df_tab = delay_table(nchans, f_top, df, ts, fine)[:, tops]",
+     "df_tab = delay_table(nchans, f_top, df, ts, fine)[:, np.minimum(tops + cps - 1, nchans - 1)]"),
+    ("P16 nominal index rounded", P, "np.floor((fine - dm_lo) / dsub)", "np.round((fine - dm_lo) / dsub)"),
+    ("P17 binning ignored in delays", P, "        ts = t_samp * b\n", "        ts = t_samp\n"),
     ("P11 threshold strict", P, "t = np.nonzero(best >= nsigma)[0]", "t = np.nonzero(best > nsigma)[0]"),
     ("P12 corner flip ignored", P, "    if flip:\n        x = x[:, ::-1]", "    if False:\n        x = x[:, ::-1]"),
 ]
