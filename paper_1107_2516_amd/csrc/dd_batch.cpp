@@ -1,8 +1,13 @@
 // Batches: many beams (each with its own plan, input and output) processed by
 // one persistent kernel launch.  The launch (counter reset kernel + persistent
-// kernel) is recorded into a HIP graph on first use and replayed afterwards;
-// dd_batch_update rewrites the device descriptor table in place, so new
-// buffers of the same shapes need no re-capture.
+// kernel) is recorded into a HIP graph on first use and replayed afterwards.
+//
+// The device descriptor table is double-buffered: each of the two slots has
+// its own table, work counters, graph and a completion event recorded after
+// every replay.  dd_batch_update writes the slot the latest replay did not
+// use, after that slot's previous replay has completed, and makes it current;
+// so an update never rewrites a table that a replay still in flight on some
+// stream may read, and new buffers of the same shapes need no re-capture.
 #include <algorithm>
 #include <cstring>
 
@@ -14,12 +19,17 @@ struct dd_batch {
   dd::TileShape shape;
   dd::BatchLaunch bl;
   int device = 0;
-  void* d_params = nullptr;
-  int32_t* d_first = nullptr;
-  unsigned* d_counters = nullptr;
+  int32_t* d_first = nullptr;  // prefix sums of work items (fixed between configures)
+  struct Slot {
+    void* d_params = nullptr;       // per-beam kernel parameters
+    unsigned* d_counters = nullptr; // the persistent kernel's work counters
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;      // recorded after the slot's latest replay
+    bool launched = false;
+  } slot[2];
+  int cur = 0;  // slot used by the next replay
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
   std::mutex mu;
   ~dd_batch();
 };
@@ -55,37 +65,53 @@ std::vector<ExecArgs> exec_args(const std::vector<dd_batch_item>& items) {
   return a;
 }
 
-void drop_graph(dd_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+void drop_graphs(dd_batch* b) {
+  for (auto& sl : b->slot) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    sl.exec = nullptr;
+    sl.graph = nullptr;
+  }
 }
 
-// (Re)build the launch for shape s and upload its descriptor table.
+// Block until no replay of either slot is in flight.
+dd_status wait_idle(dd_batch* b) {
+  for (auto& sl : b->slot)
+    if (sl.launched) DD_HIP(hipEventSynchronize(sl.done));
+  return DD_OK;
+}
+
+// (Re)build the launch for shape s and upload its descriptor table to both
+// slots (after every replay in flight has completed).
 dd_status configure(dd_batch* b, const TileShape& s) {
   BatchLaunch bl;
   std::vector<ExecArgs> a = exec_args(b->items);
   dd_status st = batch_prepare(s, b->in_t, a.data(), static_cast<int>(a.size()), &bl);
   if (st != DD_OK) return st;
-  if (!b->d_params) {
-    DD_HIP(hipMalloc(&b->d_params, bl.params.size()));
+  st = wait_idle(b);
+  if (st != DD_OK) return st;
+  if (!b->d_first) {
     DD_HIP(hipMalloc(&b->d_first, bl.first_item.size() * sizeof(int32_t)));
-    DD_HIP(hipMalloc(&b->d_counters, 64 * sizeof(unsigned)));
+    for (auto& sl : b->slot) {
+      DD_HIP(hipMalloc(&sl.d_params, bl.params.size()));
+      DD_HIP(hipMalloc(&sl.d_counters, 64 * sizeof(unsigned)));
+      DD_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    }
   }
-  DD_HIP(hipMemcpy(b->d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice));
+  for (auto& sl : b->slot)
+    DD_HIP(hipMemcpy(sl.d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice));
   DD_HIP(hipMemcpy(b->d_first, bl.first_item.data(), bl.first_item.size() * sizeof(int32_t),
                    hipMemcpyHostToDevice));
-  drop_graph(b);
+  drop_graphs(b);
   b->bl = std::move(bl);
   b->shape = s;
   return DD_OK;
 }
 
-dd_status capture(dd_batch* b) {
+dd_status capture(dd_batch* b, dd_batch::Slot& sl) {
   if (!b->cap_stream) DD_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   DD_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  dd_status st = batch_enqueue(b->bl, b->d_params, b->d_first, b->d_counters, b->cap_stream);
+  dd_status st = batch_enqueue(b->bl, sl.d_params, b->d_first, sl.d_counters, b->cap_stream);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   if (st != DD_OK) {
@@ -93,8 +119,8 @@ dd_status capture(dd_batch* b) {
     return st;
   }
   if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
-  b->graph = g;
-  DD_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  sl.graph = g;
+  DD_HIP(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0));
   return DD_OK;
 }
 
@@ -107,6 +133,10 @@ dd_status batch_time_shape(dd_batch* b, const TileShape& s, hipStream_t stream, 
   std::vector<ExecArgs> a = exec_args(b->items);
   dd_status st = batch_prepare(s, b->in_t, a.data(), static_cast<int>(a.size()), &bl);
   if (st != DD_OK) return st;
+  // the timing runs share the current slot's counters: no replay may be in flight
+  st = wait_idle(b);
+  if (st != DD_OK) return st;
+  unsigned* counters = b->slot[b->cur].d_counters;
   void* d_params = nullptr;
   int32_t* d_first = nullptr;
   DD_HIP(hipMalloc(&d_params, bl.params.size()));
@@ -120,10 +150,10 @@ dd_status batch_time_shape(dd_batch* b, const TileShape& s, hipStream_t stream, 
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) {
-    st = batch_enqueue(bl, d_params, d_first, b->d_counters, stream);  // warm-up
+    st = batch_enqueue(bl, d_params, d_first, counters, stream);  // warm-up
     if (st == DD_OK) e = hipEventRecord(e0, stream);
     for (int r = 0; st == DD_OK && e == hipSuccess && r < reps; r++)
-      st = batch_enqueue(bl, d_params, d_first, b->d_counters, stream);
+      st = batch_enqueue(bl, d_params, d_first, counters, stream);
     if (st == DD_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
     if (st == DD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
     if (st == DD_OK && e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -151,11 +181,15 @@ dd_batch::~dd_batch() {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(device);
-  dd::drop_graph(this);
+  (void)dd::wait_idle(this);
+  dd::drop_graphs(this);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  (void)hipFree(d_params);
+  for (auto& sl : slot) {
+    (void)hipFree(sl.d_params);
+    (void)hipFree(sl.d_counters);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
   (void)hipFree(d_first);
-  (void)hipFree(d_counters);
   (void)hipSetDevice(cur);
 }
 
@@ -221,8 +255,13 @@ dd_status dd_batch_update(dd_batch* b, const dd_batch_item* items, int32_t n) {
       b->items = keep;
       return dd::set_error(DD_ERR_STATE, "batch layout changed unexpectedly");
     }
-    // same layout: only the pointers change; the captured graph reads the table
-    DD_HIP(hipMemcpy(b->d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice));
+    // same layout: only the pointers change.  Write the slot the latest
+    // replay did not use, once its own previous replay has completed, and
+    // make it current; a replay still in flight keeps reading the old table.
+    dd_batch::Slot& nx = b->slot[b->cur ^ 1];
+    if (nx.launched) DD_HIP(hipEventSynchronize(nx.done));
+    DD_HIP(hipMemcpy(nx.d_params, bl.params.data(), bl.params.size(), hipMemcpyHostToDevice));
+    b->cur ^= 1;
     b->bl.params = std::move(bl.params);
     return DD_OK;
   } catch (const std::bad_alloc&) {
@@ -236,11 +275,17 @@ dd_status dd_batch_launch(dd_batch* b, void* stream) {
   try {
     if (!b) return dd::set_error(DD_ERR_INVALID_ARG, "batch is NULL");
     std::lock_guard<std::mutex> lk(b->mu);
-    if (!b->exec) {
-      dd_status st = dd::capture(b);
+    dd_batch::Slot& sl = b->slot[b->cur];
+    if (!sl.exec) {
+      dd_status st = dd::capture(b, sl);
       if (st != DD_OK) return st;
     }
-    DD_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    // a replay of the same slot still in flight on another stream shares the
+    // work counters: this replay starts after it
+    if (sl.launched) DD_HIP(hipStreamWaitEvent(static_cast<hipStream_t>(stream), sl.done, 0));
+    DD_HIP(hipGraphLaunch(sl.exec, static_cast<hipStream_t>(stream)));
+    DD_HIP(hipEventRecord(sl.done, static_cast<hipStream_t>(stream)));
+    sl.launched = true;
     return DD_OK;
   } catch (...) {
     return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");

@@ -83,6 +83,37 @@ def test_batch_graph_replays_and_update():
             assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t)), rep
 
 
+def test_batch_update_while_replay_in_flight():
+    """An update issued right after a launch on a non-blocking stream, with no
+    host synchronisation in between, must not change the buffers that launch
+    uses: the first replay writes the old outputs from the old inputs, the
+    second the new outputs from the new inputs."""
+    beams = _beams("u8", 6)
+    plans = [dd.Plan.from_delays(t) for t, _ in beams]
+    xs = [torch.from_numpy(x).cuda() for _, x in beams]
+    b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
+    old_out = list(b.outputs)
+    g = np.random.default_rng(7)
+    new_x = [make_input(g, "u8", x.shape[0], x.shape[1]) for _, x in beams]
+    new_in = [torch.from_numpy(x).cuda() for x in new_x]
+    new_out = [torch.full_like(o, -3) for o in old_out]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()  # non-blocking, default priority
+    for rep in range(3):
+        for o in old_out + new_out:
+            o.fill_(-5)
+        torch.cuda.synchronize()
+        b.update(inputs=xs, outputs=old_out)
+        b.launch(s)
+        b.update(inputs=new_in, outputs=new_out)  # no host sync with the launch above
+        b.launch(s)
+        s.synchronize()
+        for o, (t, x) in zip(old_out, beams):
+            assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t)), rep
+        for o, (t, _), x in zip(new_out, beams, new_x):
+            assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t)), rep
+
+
 def test_batch_update_rejects_shape_change():
     beams = _beams("u8", 4)
     plans = [dd.Plan.from_delays(t) for t, _ in beams]
