@@ -149,11 +149,17 @@ dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, 
                           dd_batch** out);
 
 /* Point the batch at new buffers of the same shapes (same plans, nsamp and
- * strides, same n); the captured graph is kept.  DD_ERR_INVALID_ARG if any
- * shape differs. */
+ * strides, same n); the captured graphs are kept.  DD_ERR_INVALID_ARG if any
+ * shape differs.  The batch keeps two descriptor tables and alternates between
+ * them: the update writes the table the latest launch did not use, first
+ * waiting (on the host) for that table's own previous launch to complete, so
+ * a launch still in flight keeps its old buffers and no host synchronisation
+ * with the latest launch is needed. */
 dd_status dd_batch_update(dd_batch* batch, const dd_batch_item* items, int32_t n);
 
-/* Enqueue the whole batch on `stream` (graph replay). */
+/* Enqueue the whole batch on `stream` (graph replay).  Stream-ordered; a
+ * launch that uses the same descriptor table as one still in flight on
+ * another stream starts after it (they share work counters). */
 dd_status dd_batch_launch(dd_batch* batch, void* stream);
 
 /* Use tile shape *cfg for every beam of the batch (its graph is re-recorded
@@ -243,9 +249,15 @@ dd_status dd_serve_create(const dd_serve_config* cfg, void* d_arena, size_t aren
 
 /*
  * Register a beam that streams data for `plan`, in chunks of at most
- * max_chunk samples.  Reserves the beam's carry: the last max_shift samples
- * of every channel stay on the device between chunks (section 3, "Maximum
- * shift").  DD_ERR_TOO_LARGE if the carry does not fit the arena.
+ * max_chunk samples.  Reserves the beam's ring of 2 max_shift + max_chunk
+ * (+ up to 127) samples per channel in the arena: the carry, the last samples
+ * later outputs need (at most max_shift per channel, section 3, "Maximum
+ * shift"), stays on the device between chunks, and is moved to the front of
+ * the ring only when the next chunk would pass its end.  DD_ERR_TOO_LARGE if
+ * the ring does not fit the arena, or if, with every beam's ring in place,
+ * the rest of the arena could not hold one largest chunk of some beam (its
+ * device copy plus its ndms x (max_chunk + 3, rounded up to 64) output),
+ * since such a chunk could never be admitted.
  */
 dd_status dd_serve_add_beam(dd_server* srv, const dd_plan* plan, int64_t max_chunk, int32_t* beam);
 
@@ -258,7 +270,8 @@ dd_status dd_serve_add_beam(dd_server* srv, const dd_plan* plan, int64_t max_chu
  * restarts the beam (its carry is dropped and it warms up again).  Chunks of
  * one beam must be submitted from one thread at a time.
  * DD_ERR_AGAIN when the queue or the staging pool is full (poll, release and
- * retry), DD_ERR_TOO_LARGE when nsamp exceeds the beam's max_chunk,
+ * retry), DD_ERR_TOO_LARGE when nsamp exceeds the beam's max_chunk or the
+ * chunk is larger than the whole staging pool (it could never be queued),
  * DD_ERR_NOT_FOUND for an unknown beam.
  */
 dd_status dd_serve_submit(dd_server* srv, int32_t beam, const void* h_chunk, int64_t nsamp,
@@ -402,6 +415,39 @@ dd_status dd_channelise(const float* d_volt, int64_t nsamp, int32_t nsub, int64_
 dd_status dd_corner_turn(const void* d_in, dd_dtype type, int64_t nsamp, int32_t nchans,
                          int64_t in_stride, int32_t flip, void* d_out, int64_t out_stride,
                          void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Host test hooks: the FP32 threaded-jump kernel's table                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The FP32 threaded-jump kernel (tile variant 6) serves each wavefront's dw
+ * DMs from one register window per channel: every DM's add run is a block of
+ * code whose window offset is fixed, and the host table entry of each
+ * (tile, channel, wavefront, DM) names that block, so the kernel jumps
+ * through the entries.  An entry outside the block table would be a jump
+ * into arbitrary code; the library therefore checks every table before it
+ * uploads it, and these two pure host functions expose the builder and the
+ * checker so that tests can plant wrong entries.  No GPU is used.
+ *
+ * dd_jump_table_build: from ngroups groups of dw shifts rel[g*dw + j] (>= 0,
+ * relative to the staged window of the group's channel) writes
+ * entries[g*2*dw + j] (block byte offset) and entries[g*2*dw + dw + j]
+ * (window start, samples, a multiple of 4) for the block table of window
+ * `wmax` registers and k adds per block.  dw in {4, 8}, k a multiple of 4,
+ * wmax a multiple of 4 and >= k + 4.  DD_ERR_INVALID_ARG for other shapes or
+ * a negative shift.
+ *
+ * dd_jump_table_check: DD_OK when every entry names a block of its own DM's
+ * slot (the first DM's a window load), every window start is a multiple of 4
+ * in [0, rel], and the window the entries load, read at each block's fixed
+ * offset, yields exactly rel for every DM; DD_ERR_STATE otherwise
+ * (dd_last_error says which rule failed).
+ */
+dd_status dd_jump_table_build(const int32_t* rel, int64_t ngroups, int32_t dw, int32_t k,
+                              int32_t wmax, int32_t* entries);
+dd_status dd_jump_table_check(const int32_t* entries, const int32_t* rel, int64_t ngroups,
+                              int32_t dw, int32_t k, int32_t wmax);
 
 /* ------------------------------------------------------------------------ */
 

@@ -118,6 +118,8 @@ _SIGS = {
     "dd_subband_sizes": [_P, _I64, _P, ctypes.POINTER(ctypes.c_size_t)],
     "dd_subband_execute": [_P, _P, _I64, _I64, _P, _I64, _P, ctypes.c_size_t, _P],
     "dd_subband_plan_destroy": [_P],
+    "dd_jump_table_build": [_P, _I64, _I32, _I32, _I32, _P],
+    "dd_jump_table_check": [_P, _P, _I64, _I32, _I32, _I32],
 }
 
 
@@ -379,7 +381,7 @@ class Server:
     """Streaming server: chunks of many beams, continuous batching on the GPU.
 
     arena: a uint8 CUDA tensor whose memory the server sub-allocates (beam
-    carries, chunk outputs); it must outlive the server.
+    rings, chunk staging and outputs); it must outlive the server.
     """
 
     def __init__(self, arena, in_dtype, max_inflight=8, queue_capacity=256, nstreams=4,
@@ -431,8 +433,9 @@ class Server:
         torch = _torch()
         esize = 4
         off = result.d_out - self.arena.data_ptr()
-        flat = self.arena[off: off + plan.ndms * result.out_stride * esize].view(self.out_dtype)
-        return flat.view(plan.ndms, result.out_stride)[:, : result.nout]
+        n = (plan.ndms - 1) * result.out_stride + result.nout  # elements the rows span
+        flat = self.arena[off: off + n * esize].view(self.out_dtype)
+        return flat.as_strided((plan.ndms, result.nout), (result.out_stride, 1))
 
     def release(self, ticket):
         _check(lib().dd_serve_release(self._h, int(ticket)))

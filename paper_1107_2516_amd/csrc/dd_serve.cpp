@@ -1,28 +1,37 @@
 // Streaming server: continuous batching of filterbank chunks from many beams.
 //
-// Each beam owns a device buffer of (max_shift + max_chunk) samples per
-// channel holding its overlap carry (the last max_shift samples it has
-// received, section 3 "Maximum shift") followed by the newest chunk.  A chunk
-// of n samples that brings the beam's total to S emits the outputs for
-// absolute times [E_prev, E_new) with E = max(0, S - max_shift); while fewer
-// than max_shift + 1 samples have arrived the beam is warming up and emits
-// nothing.  After the de-dispersion the new carry is moved to the front of
-// the buffer through a per-stream temporary.
+// Each beam owns a device ring of cap = 2 max_shift + max_chunk (+64) samples
+// per channel row.  It holds the beam's overlap carry (the last samples it has
+// received that later outputs still need, at most max_shift of them, section 3
+// "Maximum shift") at buffer position h, and each new chunk is placed right
+// after it.  A chunk of n samples that brings the beam's total to S emits the
+// outputs for absolute times [E_prev, E_new) with E = max(0, S - max_shift);
+// while fewer than max_shift + 1 samples have arrived the beam is warming up
+// and emits nothing.  After a chunk the carry simply stays where it is (h
+// advances by the chunk's output count); only when the next chunk would run
+// past the end of the ring is the carry slid to the front, one device copy
+// every few chunks, and because h > max_shift + 3 at that point the source and
+// destination never overlap.  De-dispersion starts at h rounded down to a
+// whole dword of samples, so every execute reads dword-aligned rows; the up to
+// three extra outputs this produces at the front are written but not reported.
 //
-// All device memory (beam buffers, chunk outputs, temporaries) is
+// All device memory (beam rings, chunk staging, chunk outputs) is
 // sub-allocated from the caller's arena; a chunk is admitted only when its
-// output fits (the memory rule of section 3, "Processable Samples").  Chunks
-// are staged in a pinned host pool at submit time.  A scheduler thread admits
-// chunks in arrival order (a beam's chunks strictly in order, other beams may
-// overtake a chunk that is waiting for memory) when the arena has room for
-// the chunk's device copy and its output, and enqueues
+// output fits (the memory rule of section 3, "Processable Samples"), and a
+// beam is accepted only if its largest chunk could be admitted once every
+// other chunk is released.  Chunks are staged in a pinned host pool at submit
+// time.  A scheduler thread admits chunks in arrival order (a beam's chunks
+// strictly in order, other beams may overtake a chunk that is waiting for
+// memory) when the arena has room for the chunk's device copy and its output,
+// and enqueues
 //   host->device copy into the chunk's device staging (one copy stream, so
 //     copies run ahead in admission order while earlier chunks compute),
-//   then on the beam's stream: wait for that copy, place the chunk after the
-//     beam's carry, de-dispersion, carry move, completion event
+//   then on the beam's stream: wait for that copy, slide the carry if the ring
+//     wraps, place the chunk after the carry, de-dispersion, completion event
 // (beams are spread over the server's streams, so work of different beams
-// overlaps on the device while others are admitted), and retires chunks as
-// their events complete.
+// overlaps on the device while others are admitted).  A retire thread blocks
+// on the oldest chunk's completion event (a blocking-sync event, no polling)
+// and retires every chunk whose work has completed.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -119,6 +128,20 @@ class RangeAlloc {
     for (auto& f : free_) m = std::max(m, f.second);
     return m;
   }
+  // Take [off, off + bytes) (rounded to granules), which must be free.
+  bool take(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (off >= it->first && off + bytes <= it->first + it->second) {
+        const size_t a = it->first, e = it->first + it->second;
+        it = free_.erase(it);
+        if (off + bytes < e) it = free_.emplace(it, off + bytes, e - off - bytes);
+        if (a < off) free_.emplace(it, a, off - a);
+        return true;
+      }
+    }
+    return false;
+  }
 
  private:
   std::list<std::pair<size_t, size_t>> free_;
@@ -133,6 +156,7 @@ struct Chunk {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int32_t status = DD_OK;
   int64_t t_first = 0, nout = 0, out_stride = 0;
+  int64_t lead = 0;  // extra outputs at the front of the output rows (dword alignment)
   size_t out_off = 0, out_bytes = 0;
   void* d_out = nullptr;
   size_t stage_off = 0, stage_bytes = 0;  // device copy of the chunk (arena)
@@ -144,14 +168,22 @@ struct Chunk {
 
 struct Beam {
   const dd_plan* plan = nullptr;
-  int64_t max_chunk = 0, cap = 0;  // cap: samples per channel row of the buffer
+  int64_t max_chunk = 0, cap = 0;  // cap: samples per channel row of the ring
   size_t buf_off = 0, buf_bytes = 0;
   unsigned char* d_buf = nullptr;
   int64_t S = 0, E = 0;     // samples enqueued, outputs emitted (absolute)
+  int64_t h = 0;            // ring position of absolute sample E
   int64_t next_seq = 0;     // expected seq of the next submitted chunk
   int stream = 0;
   int pending = 0;          // submitted, not yet admitted
+  size_t worst = 0;         // staging + output bytes of a largest chunk
 };
+
+// Samples per 32-bit word for the server's input type; ring positions of
+// de-dispersion starts are rounded down to a multiple of it.
+int64_t samples_per_dword(size_t esize) { return esize >= 4 ? 1 : static_cast<int64_t>(4 / esize); }
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 }  // namespace dd
@@ -161,14 +193,13 @@ struct dd_server {
   size_t esize = 1, osize = 4;
   unsigned char* arena = nullptr;
   dd::RangeAlloc dev_alloc;
+  dd::RangeAlloc reserved;  // the arena with only the beam rings allocated
   unsigned char* pinned = nullptr;
   size_t pinned_bytes = 0;
   dd::RangeAlloc host_alloc;
   std::vector<dd::Beam> beams;
   std::vector<hipStream_t> streams;
   hipStream_t copy_stream = nullptr;  // host -> device copies, in admission order
-  std::vector<unsigned char*> temps;  // per stream, carry-move temporary
-  std::vector<size_t> temp_size;
   std::deque<dd::Chunk*> pending;
   std::vector<dd::Chunk*> inflight;
   std::unordered_map<uint64_t, dd::Chunk*> done;  // finished, not yet polled or released
@@ -176,13 +207,21 @@ struct dd_server {
   uint64_t next_ticket = 1;
   int device = 0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  // cv_work: admission may progress (submit, release, retirement);
+  // cv_inflight: a chunk was admitted; cv_done: a chunk finished
+  std::condition_variable cv_work, cv_inflight, cv_done;
+  uint64_t work_gen = 0;  // bumped with every cv_work notification
   bool stop = false;
-  std::thread worker;
+  std::thread worker, retirer;
   ~dd_server();
   void run();
+  void run_retire();
   bool admit_locked(dd::Chunk* c);
   void retire_locked();
+  void wake_admission_locked() {
+    work_gen++;
+    cv_work.notify_all();
+  }
 };
 
 namespace dd {
@@ -191,39 +230,46 @@ namespace {
 dd_status enqueue_chunk(dd_server* s, Beam& b, Chunk* c, hipStream_t st) {
   const dd_plan* plan = b.plan;
   const int64_t nch = plan->nchans;
-  const int64_t carry = b.S - b.E;  // samples at the front of the buffer
+  const size_t es = s->esize;
+  const size_t pitch = static_cast<size_t>(b.cap) * es;
+  const int64_t carry = b.S - b.E;  // samples at ring positions [h, h + carry)
   // host -> device on the copy stream, into the chunk's own device staging,
   // so that it runs ahead while earlier chunks are de-dispersed; then, on the
   // beam's stream, the chunk goes right after the carry
-  const size_t row = static_cast<size_t>(c->nsamp) * s->esize;
+  const size_t row = static_cast<size_t>(c->nsamp) * es;
   DD_HIP(hipMemcpyAsync(c->d_stage, s->pinned + c->h_off, row * static_cast<size_t>(nch),
                         hipMemcpyHostToDevice, s->copy_stream));
   DD_HIP(hipEventRecord(c->ev_copy, s->copy_stream));
   DD_HIP(hipStreamWaitEvent(st, c->ev_copy, 0));
-  DD_HIP(hipMemcpy2DAsync(b.d_buf + carry * s->esize, static_cast<size_t>(b.cap) * s->esize,
-                          c->d_stage, row, row, static_cast<size_t>(nch), hipMemcpyDeviceToDevice,
-                          st));
+  const int64_t spd = samples_per_dword(es);
+  if (b.h + carry + c->nsamp > b.cap) {
+    // slide the carry (from its dword-aligned start) to the front of the
+    // ring.  Here h > cap - carry - nsamp >= max_shift + 64 >= carry + 3, so
+    // the source lies wholly after the destination
+    const int64_t a = b.h - b.h % spd;
+    const int64_t w = b.h - a + carry;
+    if (a < w) return set_error(DD_ERR_STATE, "ring slide would overlap");
+    if (w > 0)
+      DD_HIP(hipMemcpy2DAsync(b.d_buf, pitch, b.d_buf + a * es, pitch, static_cast<size_t>(w) * es,
+                              static_cast<size_t>(nch), hipMemcpyDeviceToDevice, st));
+    b.h -= a;
+  }
+  DD_HIP(hipMemcpy2DAsync(b.d_buf + (b.h + carry) * es, pitch, c->d_stage, row, row,
+                          static_cast<size_t>(nch), hipMemcpyDeviceToDevice, st));
   const int64_t S2 = b.S + c->nsamp;
   const int64_t E2 = std::max<int64_t>(0, S2 - plan->max_shift);
   c->t_first = b.E;
   c->nout = E2 - b.E;
   if (c->nout > 0) {
-    const int64_t len = S2 - b.E;  // buffer samples holding absolute times [E, S2)
-    dd_status st2 = dd_execute(plan, b.d_buf, s->cfg.in_t, len, b.cap, c->d_out, s->cfg.out_t,
-                               c->out_stride, st);
+    // de-dispersion from the dword-aligned ring position at or before h: the
+    // first `lead` outputs repeat already emitted times and are not reported
+    const int64_t a = b.h - b.h % spd;
+    c->lead = b.h - a;
+    const int64_t len = b.h + carry + c->nsamp - a;  // = lead + S2 - E
+    dd_status st2 = dd_execute(plan, b.d_buf + a * es, s->cfg.in_t, len, b.cap, c->d_out,
+                               s->cfg.out_t, c->out_stride, st);
     if (st2 != DD_OK) return st2;
-    // the new carry, absolute [E2, S2), moves to the front of the buffer
-    const int64_t keep = S2 - E2;
-    const int64_t from = E2 - b.E;
-    if (keep > 0 && from > 0) {
-      unsigned char* tmp = s->temps[b.stream];
-      const size_t row = static_cast<size_t>(keep) * s->esize;
-      DD_HIP(hipMemcpy2DAsync(tmp, row, b.d_buf + from * s->esize,
-                              static_cast<size_t>(b.cap) * s->esize, row, static_cast<size_t>(nch),
-                              hipMemcpyDeviceToDevice, st));
-      DD_HIP(hipMemcpy2DAsync(b.d_buf, static_cast<size_t>(b.cap) * s->esize, tmp, row, row,
-                              static_cast<size_t>(nch), hipMemcpyDeviceToDevice, st));
-    }
+    b.h += c->nout;
   }
   b.S = S2;
   b.E = E2;
@@ -239,6 +285,7 @@ bool dd_server::admit_locked(dd::Chunk* c) {
   if (c->restart) {
     b.S = 0;
     b.E = 0;
+    b.h = 0;
   }
   const int64_t S2 = b.S + c->nsamp;
   const int64_t E2 = std::max<int64_t>(0, S2 - b.plan->max_shift);
@@ -247,7 +294,8 @@ bool dd_server::admit_locked(dd::Chunk* c) {
   if (!dev_alloc.alloc(c->stage_bytes, &c->stage_off)) return false;  // wait for releases
   c->d_stage = arena + c->stage_off;
   if (nout > 0) {
-    c->out_stride = (nout + 63) & ~int64_t(63);
+    // room for the up to 3 leading outputs of the dword-aligned start
+    c->out_stride = (nout + 3 + 63) & ~int64_t(63);
     c->out_bytes = static_cast<size_t>(b.plan->ndms) * c->out_stride * osize;
     if (!dev_alloc.alloc(c->out_bytes, &c->out_off)) {  // wait for releases
       dev_alloc.release(c->stage_off, c->stage_bytes);
@@ -263,6 +311,7 @@ bool dd_server::admit_locked(dd::Chunk* c) {
     // the beam's buffer state is unknown after a failed enqueue: restart it
     b.S = 0;
     b.E = 0;
+    b.h = 0;
   }
   return true;
 }
@@ -283,8 +332,7 @@ void dd_server::retire_locked() {
     c->d_stage = nullptr;
     done[c->ticket] = c;
     ready.push_back(c->ticket);
-    inflight[i] = inflight.back();
-    inflight.pop_back();
+    inflight.erase(inflight.begin() + static_cast<std::ptrdiff_t>(i));  // keep admission order
     cv_done.notify_all();
   }
 }
@@ -293,6 +341,7 @@ void dd_server::run() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
+    const uint64_t gen = work_gen;
     // admission: arrival order, a beam's chunks in order, others may overtake
     std::vector<int> blocked(beams.size(), 0);
     for (auto it = pending.begin(); it != pending.end();) {
@@ -327,20 +376,30 @@ void dd_server::run() {
         cv_done.notify_all();
       } else {
         inflight.push_back(c);
+        cv_inflight.notify_all();
       }
       it = pending.erase(it);
     }
+    // sleep until a submit, a release or a retirement may let admission progress
+    cv_work.wait(lk, [&] { return stop || work_gen != gen; });
+  }
+}
+
+// Retire thread: blocks (without polling) on the oldest chunk's completion
+// event, then retires every chunk whose work has completed.
+void dd_server::run_retire() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  while (true) {
+    cv_inflight.wait(lk, [&] { return stop || !inflight.empty(); });
+    if (inflight.empty()) break;  // stop requested and nothing in flight
+    hipEvent_t ev = inflight.front()->ev;
+    lk.unlock();
+    (void)hipEventSynchronize(ev);  // the chunk stays in flight, so ev stays valid
+    lk.lock();
+    const size_t before = inflight.size();
     retire_locked();
-    if (inflight.empty() && pending.empty()) {
-      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
-    } else if (inflight.empty()) {
-      // everything pending waits for arena memory: sleep until a release
-      cv_work.wait_for(lk, std::chrono::milliseconds(5));
-    } else {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-      lk.lock();
-    }
+    if (inflight.size() != before) wake_admission_locked();
   }
 }
 
@@ -348,9 +407,11 @@ dd_server::~dd_server() {
   {
     std::lock_guard<std::mutex> lk(mu);
     stop = true;
+    wake_admission_locked();
+    cv_inflight.notify_all();
   }
-  cv_work.notify_all();
   if (worker.joinable()) worker.join();
+  if (retirer.joinable()) retirer.join();
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(device);
@@ -392,15 +453,15 @@ dd_status dd_serve_create(const dd_serve_config* cfg, void* d_arena, size_t aren
     DD_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->pinned), s->pinned_bytes, hipHostMallocDefault));
     s->host_alloc.reset(s->pinned_bytes);
     DD_HIP(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
+    s->reserved.reset(arena_bytes);
     for (int i = 0; i < cfg->nstreams; i++) {
       hipStream_t st = nullptr;
       DD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
       s->streams.push_back(st);
-      s->temps.push_back(nullptr);
-      s->temp_size.push_back(0);
     }
     dd_server* raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
+    s->retirer = std::thread([raw] { raw->run_retire(); });
     *out = s.release();
     return DD_OK;
   } catch (const std::bad_alloc&) {
@@ -418,26 +479,30 @@ dd_status dd_serve_add_beam(dd_server* s, const dd_plan* plan, int64_t max_chunk
     dd::Beam b;
     b.plan = plan;
     b.max_chunk = max_chunk;
-    b.cap = (plan->max_shift + max_chunk + 63) & ~int64_t(63);
+    b.cap = (2 * static_cast<int64_t>(plan->max_shift) + max_chunk + 64 + 63) & ~int64_t(63);
     b.buf_bytes = static_cast<size_t>(b.cap) * plan->nchans * s->esize;
+    // a largest chunk's device staging and output (with its leading outputs)
+    b.worst = dd::round256(static_cast<size_t>(max_chunk) * plan->nchans * s->esize) +
+              dd::round256(static_cast<size_t>(plan->ndms) *
+                           static_cast<size_t>((max_chunk + 3 + 63) & ~int64_t(63)) * s->osize);
     if (!s->dev_alloc.alloc(b.buf_bytes, &b.buf_off))
-      return dd::set_error(DD_ERR_TOO_LARGE, "the beam's carry buffer does not fit the arena");
+      return dd::set_error(DD_ERR_TOO_LARGE, "the beam's ring buffer does not fit the arena");
+    if (!s->reserved.take(b.buf_off, b.buf_bytes)) {
+      s->dev_alloc.release(b.buf_off, b.buf_bytes);
+      return dd::set_error(DD_ERR_STATE, "arena bookkeeping out of step");
+    }
+    // every beam's largest chunk must still be admissible once all chunks
+    // are released (staging and output counted in one free range)
+    size_t need = b.worst;
+    for (const dd::Beam& o : s->beams) need = std::max(need, o.worst);
+    if (need > s->reserved.largest()) {
+      s->dev_alloc.release(b.buf_off, b.buf_bytes);
+      s->reserved.release(b.buf_off, b.buf_bytes);
+      return dd::set_error(DD_ERR_TOO_LARGE,
+                           "the arena left beside the beam rings cannot hold a largest chunk");
+    }
     b.d_buf = s->arena + b.buf_off;
     b.stream = static_cast<int>(s->beams.size()) % s->cfg.nstreams;
-    // the carry-move temporary of the beam's stream must hold this beam's carry
-    const size_t need = std::max<size_t>(
-        static_cast<size_t>(plan->max_shift) * plan->nchans * s->esize, 256);
-    if (need > s->temp_size[b.stream]) {
-      size_t off = 0;
-      if (!s->dev_alloc.alloc(need, &off)) {
-        s->dev_alloc.release(b.buf_off, b.buf_bytes);
-        return dd::set_error(DD_ERR_TOO_LARGE, "the carry temporary does not fit the arena");
-      }
-      // a smaller temporary of this stream may still be used by queued work:
-      // it stays allocated until the server is destroyed
-      s->temps[b.stream] = s->arena + off;
-      s->temp_size[b.stream] = need;
-    }
     *beam = static_cast<int32_t>(s->beams.size());
     s->beams.push_back(b);
     return DD_OK;
@@ -461,9 +526,12 @@ dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64
     if (static_cast<int32_t>(s->pending.size()) >= s->cfg.queue_capacity)
       return dd::set_error(DD_ERR_AGAIN, "submit queue full");
     const size_t bytes = static_cast<size_t>(nsamp) * b.plan->nchans * s->esize;
+    if (bytes > s->pinned_bytes)
+      return dd::set_error(DD_ERR_TOO_LARGE, "chunk larger than the whole host staging pool");
     // everything that can fail comes before the staging range is taken
     std::unique_ptr<dd::Chunk> c(new dd::Chunk());
-    hipError_t e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
+    // the completion event is waited on by the retire thread: blocking sync
+    hipError_t e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming | hipEventBlockingSync);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming);
     if (e != hipSuccess) {
       if (c->ev) (void)hipEventDestroy(c->ev);
@@ -505,7 +573,7 @@ dd_status dd_serve_submit(dd_server* s, int32_t beam, const void* h_chunk, int64
       return dd::set_error(DD_ERR_OOM, "host allocation failed");
     }
     *ticket = c.release()->ticket;
-    s->cv_work.notify_all();
+    s->wake_admission_locked();
     return DD_OK;
   } catch (const std::bad_alloc&) {
     return dd::set_error(DD_ERR_OOM, "host allocation failed");
@@ -531,7 +599,8 @@ dd_status dd_serve_poll(dd_server* s, dd_result* out, int32_t max, int32_t* n) {
     r.seq = c->seq;
     r.t_first = c->t_first;
     r.nout = c->status == DD_OK ? c->nout : 0;
-    r.d_out = c->d_out;
+    // the reported rows start after the leading outputs of the aligned start
+    r.d_out = c->d_out ? static_cast<unsigned char*>(c->d_out) + c->lead * s->osize : nullptr;
     r.out_stride = c->out_stride;
     r.t_submit = c->t_submit;
     r.t_admit = c->t_admit;
@@ -552,7 +621,7 @@ dd_status dd_serve_release(dd_server* s, uint64_t ticket) {
   if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
   delete c;
   s->done.erase(it);
-  s->cv_work.notify_all();  // memory freed: admission may proceed
+  s->wake_admission_locked();  // memory freed: admission may proceed
   return DD_OK;
 }
 

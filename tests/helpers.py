@@ -13,8 +13,8 @@ def scaled_error(y, x, delays, rows=None, t_begin=0, t_end=None):
     """Largest scaled error of GPU rows `y` (matching `rows` and the time
     window) against the oracle on input `x`."""
     ref = oracle.dedisperse(x, delays, rows=rows, t_begin=t_begin, t_end=t_end)
-    ax = np.abs(x.astype(np.float64)) if x.dtype != np.float16 else np.abs(x).astype(np.float64)
-    den = oracle.dedisperse(ax, delays, rows=rows, t_begin=t_begin, t_end=t_end)
+    # |x| is exact in the input's own type; the oracle sums it in FP64
+    den = oracle.dedisperse(np.abs(x), delays, rows=rows, t_begin=t_begin, t_end=t_end)
     y = np.asarray(y, dtype=np.float64)
     assert y.shape == ref.shape, (y.shape, ref.shape)
     err = np.abs(y - ref) / np.maximum(den, 1e-30)

@@ -47,15 +47,15 @@ def _chunks(g, nsamp, lo, hi):
     return cuts
 
 
-@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "f32", "f16"])
 def test_stream_equivalence(dtype):
-    g = np.random.default_rng(31 if dtype == "u8" else 32)
+    g = np.random.default_rng({"u8": 31, "f32": 32, "f16": 33}[dtype])
     nchans, ndms, maxd = 48, 40, 500
     tab = np.sort(rand_table(g, ndms, nchans, maxd), axis=0)
     plan = dd.Plan.from_delays(tab)
     total = 6000
     x = make_input(g, dtype, nchans, total)
-    tdt = torch.uint8 if dtype == "u8" else torch.float32
+    tdt = {"u8": torch.uint8, "f32": torch.float32, "f16": torch.float16}[dtype]
     srv = dd.Server(_arena(64 << 20), tdt, max_inflight=4, nstreams=2)
     beam = srv.add_beam(plan, max_chunk=1500)
     # a 1-sample chunk, a 7-sample chunk, then random lengths up to max_chunk
@@ -147,14 +147,14 @@ def test_admission_waits_for_memory_and_errors():
     plan = dd.Plan.from_delays(tab)
     m = int(tab.max())
     x = make_input(g, "u8", 24, 4 * 1024)
-    # arena: the beam buffer, one stream's carry temporary, room for one
-    # output and one chunk's device staging
-    cap = (m + 1024 + 63) // 64 * 64
-    need = cap * 24 + ((m * 24 + 255) // 256) * 256 + 32 * 1024 * 4 + 1024 * 24 + 4096
+    # arena: the beam's ring, room for one chunk's device staging and one
+    # output (ndms x (max_chunk + 3 rounded up to 64) int32)
+    ring = (2 * m + 1024 + 64 + 63) // 64 * 64 * 24
+    need = ring + ((1024 * 24 + 255) // 256) * 256 + 32 * ((1024 + 3 + 63) // 64 * 64) * 4 + 1024
     srv = dd.Server(_arena(need), torch.uint8, max_inflight=4, queue_capacity=3, nstreams=1)
     b = srv.add_beam(plan, 1024)
     with pytest.raises(dd.DedispError) as ei:
-        srv.add_beam(plan, 1 << 20)  # its carry buffer does not fit
+        srv.add_beam(plan, 1 << 20)  # its ring does not fit
     assert ei.value.status == dd.DD_ERR_TOO_LARGE
     with pytest.raises(dd.DedispError) as ei:
         srv.submit(b, np.zeros((24, 2000), np.uint8), 0)  # longer than max_chunk
@@ -208,8 +208,8 @@ def test_full_shape_sampled_rows():
     lens = [max_chunk, m - max_chunk, max_chunk, 1 << 14, 100003]
     g = np.random.default_rng(2518)
     x = g.integers(0, 256, size=(band.nchans, sum(lens)), dtype=np.uint8)
-    cap = (m + max_chunk + 63) // 64 * 64
-    arena = _arena(cap * band.nchans + m * band.nchans + 4 * max_chunk * 4096 * 4
+    ring = (2 * m + max_chunk + 64 + 63) // 64 * 64
+    arena = _arena(ring * band.nchans + 4 * max_chunk * 4096 * 4
                    + 2 * max_chunk * band.nchans + (64 << 20))
     srv = dd.Server(arena, torch.uint8, max_inflight=4, nstreams=2)
     b = srv.add_beam(plan, max_chunk)
@@ -227,6 +227,85 @@ def test_full_shape_sampled_rows():
         assert t_first == nxt and y.shape == (4096, pos - m - nxt)
         ref = oracle.dedisperse(x, tab, rows=rows, t_begin=nxt, t_end=pos - m)
         assert np.array_equal(y[rows].astype(np.int64), ref)
+        nxt = pos - m
+    assert nxt == sum(lens) - m
+    srv.close()
+
+
+def test_beam_whose_largest_chunk_never_fits_is_refused():
+    """A beam whose ring fits the arena but whose largest chunk (device copy
+    plus output) could never be admitted beside the rings is refused at
+    add_beam, and its ring is given back; a chunk larger than the whole host
+    staging pool is refused at submit (it could never be queued)."""
+    g = np.random.default_rng(61)
+    tab = np.sort(rand_table(g, 32, 24, 200), axis=0)
+    plan = dd.Plan.from_delays(tab)
+    m = int(tab.max())
+    ring = (2 * m + 1024 + 64 + 63) // 64 * 64 * 24
+    worst = ((1024 * 24 + 255) // 256) * 256 + 32 * ((1024 + 3 + 63) // 64 * 64) * 4
+    arena_bytes = ring + worst - 4096  # the ring fits, a largest chunk does not
+    srv = dd.Server(_arena(arena_bytes), torch.uint8, max_inflight=2, nstreams=1,
+                    host_staging_bytes=8192)
+    with pytest.raises(dd.DedispError) as ei:
+        srv.add_beam(plan, 1024)
+    assert ei.value.status == dd.DD_ERR_TOO_LARGE
+    assert srv.stats()["largest_free"] == arena_bytes // 256 * 256  # ring given back
+    b = srv.add_beam(plan, 64)  # small chunks fit
+    with pytest.raises(dd.DedispError) as ei:
+        srv.submit(b, np.zeros((24, 64), np.uint8), 0)  # 1536 bytes: fits the pool
+        srv.submit(b, np.zeros((24, 400), np.uint8), 1)  # > max_chunk
+    assert ei.value.status == dd.DD_ERR_TOO_LARGE
+    srv.drain()
+    for r in srv.poll():
+        srv.release(r.ticket)
+    srv.close()
+    srv2 = dd.Server(_arena(64 << 20), torch.uint8, max_inflight=2, nstreams=1,
+                     host_staging_bytes=4096)
+    b2 = srv2.add_beam(plan, 1024)
+    with pytest.raises(dd.DedispError) as ei:
+        srv2.submit(b2, np.zeros((24, 1000), np.uint8), 0)  # 24000 bytes > the 4096-byte pool
+    assert ei.value.status == dd.DD_ERR_TOO_LARGE
+    srv2.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_full_shape_float_sampled_rows(dtype):
+    """The streaming beam shape (2048 channels 120-180 MHz at 327.68 us, 4096
+    DMs step 0.125) with float input: a warm-up, then chunks of 2^17, 2^14 and
+    a ragged length; sampled DM rows of every output chunk within the FP
+    tolerance of the FP64 oracle, output times continuous."""
+    import synth
+    band = synth.serve_band()
+    dms = synth.dm_grid(4096, 0.125)
+    plan = dd.Plan(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    tab = oracle.delay_table(band.nchans, band.f_top, band.df, band.t_samp, dms)
+    m = int(tab.max())
+    max_chunk = 1 << 17
+    lens = [max_chunk, m - max_chunk, max_chunk, 1 << 14, 70001]
+    g = np.random.default_rng(2519)
+    x = make_input(g, dtype, band.nchans, sum(lens))
+    tdt = torch.float32 if dtype == "f32" else torch.float16
+    es = x.itemsize
+    ring = (2 * m + max_chunk + 64 + 63) // 64 * 64
+    arena = _arena(ring * band.nchans * es + 2 * max_chunk * 4096 * 4
+                   + 2 * max_chunk * band.nchans * es + (64 << 20))
+    srv = dd.Server(arena, tdt, max_inflight=2, nstreams=2, host_staging_bytes=3 << 30)
+    b = srv.add_beam(plan, max_chunk)
+    rows = [0, 33, 2047, 4095]
+    pos, nxt = 0, 0
+    for seq, n in enumerate(lens):
+        tk = srv.submit(b, x[:, pos:pos + n], seq)
+        assert tk is not None
+        got = _collect(srv, [tk])
+        t_first, y = got[tk]
+        pos += n
+        if pos <= m:
+            assert y is None
+            continue
+        assert t_first == nxt and y.shape == (4096, pos - m - nxt)
+        # the input window these outputs read: [nxt, pos)
+        e, _ = scaled_error(y[rows], x[:, nxt:pos], tab, rows=rows, t_end=pos - m - nxt)
+        assert e <= FP_TOL, e
         nxt = pos - m
     assert nxt == sum(lens) - m
     srv.close()
