@@ -166,3 +166,30 @@ const char* dd_last_error(void) { return dd::last_error_cstr(); }
 const char* dd_version(void) { return "0.1.0"; }
 
 }  // extern "C"
+
+extern "C" {
+
+static bool jump_shape_ok(int32_t dw, int32_t k, int32_t wmax) {
+  return (dw == 4 || dw == 8) && k >= 4 && k % 4 == 0 && wmax % 4 == 0 && wmax >= k + 4 &&
+         wmax <= 256;
+}
+
+dd_status dd_jump_table_build(const int32_t* rel, int64_t ngroups, int32_t dw, int32_t k,
+                              int32_t wmax, int32_t* entries) {
+  DD_GUARD_BEGIN
+  if (!rel || !entries || ngroups < 0) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  if (!jump_shape_ok(dw, k, wmax)) return dd::set_error(DD_ERR_INVALID_ARG, "bad block-table shape");
+  return dd::build_jump_entries(rel, ngroups, dd::jump_layout(dw, k, wmax), entries);
+  DD_GUARD_END
+}
+
+dd_status dd_jump_table_check(const int32_t* entries, const int32_t* rel, int64_t ngroups,
+                              int32_t dw, int32_t k, int32_t wmax) {
+  DD_GUARD_BEGIN
+  if (!rel || !entries || ngroups < 0) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+  if (!jump_shape_ok(dw, k, wmax)) return dd::set_error(DD_ERR_INVALID_ARG, "bad block-table shape");
+  return dd::check_jump_entries(entries, rel, ngroups, dd::jump_layout(dw, k, wmax));
+  DD_GUARD_END
+}
+
+}  // extern "C"

@@ -69,6 +69,8 @@ struct DeviceTables {
   std::map<std::pair<int, int>, int32_t*> ralign;
   // scheduled register-window entries, keyed by (td, DMs per wave, slack)
   std::map<std::tuple<int, int, int>, int32_t*> wintab;
+  // threaded-jump entries, keyed by (td, DMs per wave, samples per lane, window)
+  std::map<std::tuple<int, int, int, int>, int32_t*> jumptab;
 };
 
 }  // namespace dd
@@ -109,6 +111,40 @@ dd_status plan_ralign(dd_plan* plan, int td, int epd, const int32_t** out);
 // bits 8-15 zero) and start < 2^14; on DM 0, bit 30 is set when a later DM
 // of the wavefront reloads.
 dd_status plan_wintab(dd_plan* plan, int td, int dw, int slack, const int32_t** out);
+
+// Threaded-jump register window (FP32 variant 6).  Each (tile, channel,
+// wavefront) has 2*dw table words: dw block offsets (bytes from the start of
+// the step's block table) and dw window starts (samples, multiples of 4).
+// The block table holds dw*np plain blocks of pbs bytes (block (j, o): DM j
+// adds window registers o..o+k-1) and then dw*4 reload blocks of rbs bytes
+// (block (j, q): load the window at DM j's start, add registers q..q+k-1).
+// The sizes follow from the instruction encodings (see gen_window_asm.py,
+// thread_layout); the device code static_asserts that they match the
+// generated blocks.
+struct JumpLayout {
+  int dw, k, wmax, np, pbs, rbs;
+};
+constexpr JumpLayout jump_layout(int dw, int k, int wmax) {
+  return JumpLayout{dw, k, wmax, wmax - k + 1, 4 * k + 12, 8 + 2 * wmax + 4 + 8 + 4 * k + 12};
+}
+// Entries for ngroups groups of dw DMs from their shifts rel[g*dw + j]
+// relative to the staged window (>= 0): DM 0 reloads at rel & ~3, a later DM
+// keeps the window when rel - start lies in [0, wmax - k], else reloads.
+// out[g*2dw + j] = block offset, out[g*2dw + dw + j] = window start.
+dd_status build_jump_entries(const int32_t* rel, int64_t ngroups, const JumpLayout& L,
+                             int32_t* out);
+// Check entries against the shifts they must realise, by running the window
+// schedule they encode: every offset must name a block of the DM's own slot
+// (DM 0: a reload block), a reload start must be a multiple of 4 in
+// [0, rel], and the window start plus the block's register offset must equal
+// rel for every DM.  An entry that fails would jump outside the block table
+// or add the wrong samples; DD_ERR_STATE names the first failure.
+dd_status check_jump_entries(const int32_t* ent, const int32_t* rel, int64_t ngroups,
+                             const JumpLayout& L);
+// Device copy (uploaded once per device and layout) of the entries of every
+// (tile, channel, wavefront) of the plan for tile height td, checked before
+// upload: [tile][channel][td/dw wavefronts][2*dw].
+dd_status plan_jumptab(dd_plan* plan, int td, const JumpLayout& L, const int32_t** out);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {

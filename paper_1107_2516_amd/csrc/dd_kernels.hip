@@ -36,6 +36,10 @@
 //  5  BodyWin:     variant 1 with the window reloads scheduled on the host
 //                  (plan_wintab), so DMs that share a window switch only the
 //                  VGPR index.
+//  6  BodyWin:     threaded-jump flavour: plain adds in code blocks whose
+//                  window offset is fixed; each DM's host-built (and
+//                  host-checked) table entry names its block, and every block
+//                  jumps straight to the next DM's (plan_jumptab).
 #include <cstring>
 #include <type_traits>
 
@@ -197,9 +201,11 @@ struct BodyLds {
 // of rel (plan_wintab), for the steps generated by gen_sched; the body is the
 // same.
 template <int DW, int K, int WMAX, int OCC_,
-          void (*STEP)(float*, const int*, unsigned, const int32_t*, int*), bool SCHED = false>
+          void (*STEP)(float*, const int*, unsigned, const int32_t*, int*), bool SCHED = false,
+          bool JUMP = false>
 struct BodyWin {
   static constexpr int TD = 4 * DW, TT = 64 * K, OCC = OCC_;
+  static constexpr int EW = JUMP ? 2 : 1;  // table words per DM and channel
   __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* lds = reinterpret_cast<float*>(smem);
@@ -232,9 +238,10 @@ struct BodyWin {
     float acc[DW * K];
 #pragma unroll
     for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
-    const int32_t* tabw = p.tab + static_cast<int64_t>(dtile) * p.nchans * TD + wave * DW;
-    int r[DW];
-    cload_dw<DW>(tabw, r);
+    const int32_t* tabw =
+        p.tab + static_cast<int64_t>(dtile) * p.nchans * TD * EW + wave * DW * EW;
+    int r[DW * EW];
+    cload_dw<DW * EW>(tabw, r);
     issue(0, 0);
     for (int s = 0; s < nstage; s++) {
       const int buf = s & 1;
@@ -243,12 +250,16 @@ struct BodyWin {
       if (s + 1 < nstage) issue(s + 1, buf ^ 1);
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
+      // one instance of the step: the threaded flavour's block table is
+      // code inside it, so the loop must not be unrolled
+#pragma unroll 1
       for (int i = 0; i < ncc; i++) {
-        int rn[DW];  // next channel's shifts, loaded by the step behind its first DM
+        int rn[DW * EW];  // next channel's entries, loaded by the step behind its first DM
         STEP(acc, r, lane_addr + static_cast<unsigned>((buf * cc_max + i) * slot * 4),
-             uniform_ptr(tabw + static_cast<int64_t>(min(c0 + i + 1, p.nchans - 1)) * TD), rn);
+             uniform_ptr(tabw + static_cast<int64_t>(min(c0 + i + 1, p.nchans - 1)) * TD * EW),
+             rn);
 #pragma unroll
-        for (int j = 0; j < DW; j++) r[j] = rn[j];
+        for (int j = 0; j < DW * EW; j++) r[j] = rn[j];
       }
     }
     float* out = static_cast<float*>(p.out);
@@ -279,6 +290,8 @@ struct BodyWin {
   static constexpr int table_epd = 0;
   // variant 5: the step reads host-scheduled window entries (plan_wintab)
   static constexpr int table_win = SCHED ? WMAX - K : 0;
+  // variant 6: the step reads threaded-jump entries (plan_jumptab)
+  static constexpr JumpLayout table_jump = JUMP ? jump_layout(DW, K, WMAX) : JumpLayout{};
 };
 
 // ---------------------------------------------------------------- variant 3
@@ -796,6 +809,17 @@ struct BodyWinX {
   static constexpr int table_ralign = EPD;
 };
 
+// The host's jump-table layout must match the generated block tables.
+#define DD_CHECK_LAYOUT(NAME, DW, K, W)                                   \
+  static_assert(jump_layout(DW, K, W).np == DD_##NAME##_NP &&             \
+                    jump_layout(DW, K, W).pbs == DD_##NAME##_PBS &&       \
+                    jump_layout(DW, K, W).rbs == DD_##NAME##_RBS,         \
+                "jump-table layout differs from the generated blocks");
+DD_CHECK_LAYOUT(T_F32_D8_K12_W48, 8, 12, 48)
+DD_CHECK_LAYOUT(T_F32_D8_K16_W56, 8, 16, 56)
+DD_CHECK_LAYOUT(T_F32_D4_K24_W48, 4, 24, 48)
+#undef DD_CHECK_LAYOUT
+
 // ------------------------------------------------------------------ kernels
 
 template <class Body>
@@ -873,6 +897,7 @@ struct Impl {
   const void* single;
   const void* batch;
   int td, tt, table_epd, table_ralign, table_win;
+  JumpLayout table_jump;  // dw == 0: not a threaded-jump body
   size_t in_size;
   bool needs_dword_rows;
 };
@@ -895,6 +920,15 @@ struct WinOf<Body, std::void_t<decltype(Body::table_win)>> {
   static constexpr int value = Body::table_win;
 };
 
+template <class Body, class = void>
+struct JumpOf {
+  static constexpr JumpLayout value{};
+};
+template <class Body>
+struct JumpOf<Body, std::void_t<decltype(Body::table_jump)>> {
+  static constexpr JumpLayout value = Body::table_jump;
+};
+
 template <class Body, typename Tin>
 Impl make_impl() {
   Impl m;
@@ -906,6 +940,7 @@ Impl make_impl() {
   m.table_epd = Body::table_epd;
   m.table_ralign = RalignOf<Body>::value;
   m.table_win = WinOf<Body>::value;
+  m.table_jump = JumpOf<Body>::value;
   m.in_size = sizeof(Tin);
   m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0;
   return m;
@@ -942,6 +977,17 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
       return *out = make_impl<BodyWin<6, 12, 64, 3, dd_s_f32_d6_k12_w64_channel, true>, float>(), true;
     if (d == 4 && k == 12)
       return *out = make_impl<BodyWin<4, 12, 40, 4, dd_s_f32_d4_k12_w40_channel, true>, float>(), true;
+  }
+  if (in_t == DD_F32 && v == 6) {
+    if (d == 8 && k == 12)
+      return *out = make_impl<BodyWin<8, 12, 48, 3, dd_t_f32_d8_k12_w48_channel, false, true>,
+                              float>(), true;
+    if (d == 8 && k == 16)
+      return *out = make_impl<BodyWin<8, 16, 56, 2, dd_t_f32_d8_k16_w56_channel, false, true>,
+                              float>(), true;
+    if (d == 4 && k == 24)
+      return *out = make_impl<BodyWin<4, 24, 48, 3, dd_t_f32_d4_k24_w48_channel, false, true>,
+                              float>(), true;
   }
   if (in_t == DD_F32 && v == 2) {
     if (d == 8 && k == 20)
@@ -1024,6 +1070,9 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
     if (st != DD_OK) return st;
   } else if (impl.table_ralign) {
     st = plan_ralign(a.plan, impl.td, impl.table_ralign, &tab);
+    if (st != DD_OK) return st;
+  } else if (impl.table_jump.dw) {
+    st = plan_jumptab(a.plan, impl.td, impl.table_jump, &tab);
     if (st != DD_OK) return st;
   } else if (impl.table_win) {
     st = plan_wintab(a.plan, impl.td, impl.td / 4, impl.table_win, &tab);

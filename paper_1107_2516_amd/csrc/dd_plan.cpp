@@ -311,6 +311,121 @@ dd_status plan_wintab(dd_plan* plan, int td, int dw, int slack, const int32_t** 
   return DD_OK;
 }
 
+dd_status build_jump_entries(const int32_t* rel, int64_t ngroups, const JumpLayout& L,
+                             int32_t* out) {
+  if (L.dw < 1 || L.k < 1 || L.np < 1 || L.wmax < L.k + 3)
+    return set_error(DD_ERR_INVALID_ARG, "bad jump-table layout");
+  const int64_t reload0 = static_cast<int64_t>(L.dw) * L.np * L.pbs;
+  for (int64_t g = 0; g < ngroups; g++) {
+    const int32_t* r = rel + g * L.dw;
+    int32_t* e = out + g * 2 * L.dw;
+    int32_t start = 0;
+    for (int j = 0; j < L.dw; j++) {
+      if (r[j] < 0) return set_error(DD_ERR_INVALID_ARG, "negative shift in a jump table");
+      const uint32_t o = static_cast<uint32_t>(r[j] - start);
+      int64_t off;
+      if (j > 0 && o <= static_cast<uint32_t>(L.wmax - L.k)) {
+        off = (static_cast<int64_t>(j) * L.np + o) * L.pbs;
+      } else {
+        start = r[j] & ~3;
+        off = reload0 + (static_cast<int64_t>(j) * 4 + (r[j] - start)) * L.rbs;
+      }
+      if (off > INT32_MAX) return set_error(DD_ERR_TOO_LARGE, "block table beyond 2 GB");
+      e[j] = static_cast<int32_t>(off);
+      e[L.dw + j] = start;
+    }
+  }
+  return DD_OK;
+}
+
+dd_status check_jump_entries(const int32_t* ent, const int32_t* rel, int64_t ngroups,
+                             const JumpLayout& L) {
+  const int64_t plain_end = static_cast<int64_t>(L.dw) * L.np * L.pbs;
+  const int64_t table_end = plain_end + static_cast<int64_t>(L.dw) * 4 * L.rbs;
+  for (int64_t g = 0; g < ngroups; g++) {
+    const int32_t* e = ent + g * 2 * L.dw;
+    const int32_t* r = rel + g * L.dw;
+    int64_t start = -1;  // no window loaded yet
+    for (int j = 0; j < L.dw; j++) {
+      const int64_t off = e[j];
+      int64_t shift;
+      if (off >= 0 && off < plain_end) {
+        if (off % L.pbs != 0 || off / L.pbs / L.np != j || start < 0)
+          return set_error(DD_ERR_STATE, "jump table: plain block of another DM, or no window");
+        shift = start + (off / L.pbs) % L.np;
+      } else if (off >= plain_end && off < table_end) {
+        const int64_t b = off - plain_end;
+        if (b % L.rbs != 0 || b / L.rbs / 4 != j)
+          return set_error(DD_ERR_STATE, "jump table: reload block of another DM");
+        const int64_t s = e[L.dw + j];
+        if (s < 0 || s % 4 != 0 || s > r[j])
+          return set_error(DD_ERR_STATE, "jump table: bad window start");
+        start = s;
+        shift = start + (b / L.rbs) % 4;
+      } else {
+        return set_error(DD_ERR_STATE, "jump table: offset outside the block table");
+      }
+      if (j == 0 && off < plain_end)
+        return set_error(DD_ERR_STATE, "jump table: the first DM must load the window");
+      if (shift != r[j]) return set_error(DD_ERR_STATE, "jump table: wrong shift");
+    }
+  }
+  return DD_OK;
+}
+
+dd_status plan_jumptab(dd_plan* plan, int td, const JumpLayout& L, const int32_t** out) {
+  if (L.dw < 1 || td % L.dw != 0) return set_error(DD_ERR_INVALID_ARG, "bad jump-table shape");
+  const TileTables* tt = nullptr;
+  dd_status st = plan_tiles(plan, td, &tt);
+  if (st != DD_OK) return st;
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(plan->mu);
+  DeviceTables& dt = plan->dev[dev];
+  const auto key = std::make_tuple(td, L.dw, L.k, L.wmax);
+  auto it = dt.jumptab.find(key);
+  if (it != dt.jumptab.end()) {
+    *out = it->second;
+    return DD_OK;
+  }
+  const int nch = plan->nchans;
+  const int ntiles = tt->ntiles;
+  const int64_t ngroups = static_cast<int64_t>(ntiles) * nch * (td / L.dw);
+  std::vector<int32_t> rel(static_cast<size_t>(ngroups) * L.dw);
+  for (int tile = 0; tile < ntiles; tile++) {
+    const int first = tile * td;
+    const int count = std::min(td, plan->ndms - first);
+    for (int c = 0; c < nch; c++) {
+      int32_t lo = INT32_MAX;
+      for (int j = 0; j < count; j++)
+        lo = std::min(lo, plan->delays[static_cast<size_t>(plan->order[first + j]) * nch + c]);
+      int32_t* r = &rel[(static_cast<size_t>(tile) * nch + c) * td];
+      for (int j = 0; j < td; j++) {
+        // padding DMs repeat the tile's first DM; their sums are not stored
+        const int src = plan->order[first + (j < count ? j : 0)];
+        r[j] = plan->delays[static_cast<size_t>(src) * nch + c] - lo;
+      }
+    }
+  }
+  // +16: a wavefront fetches its 2*dw words with one scalar load, one channel ahead
+  std::vector<int32_t> host(static_cast<size_t>(ngroups) * 2 * L.dw + 16, 0);
+  st = build_jump_entries(rel.data(), ngroups, L, host.data());
+  if (st != DD_OK) return st;
+  st = check_jump_entries(host.data(), rel.data(), ngroups, L);
+  if (st != DD_OK) return st;
+  int32_t* d = nullptr;
+  hipError_t err = hipMalloc(&d, host.size() * sizeof(int32_t));
+  if (err == hipSuccess)
+    err = hipMemcpy(d, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(d);
+    return hip_error(err, "uploading the jump table");
+  }
+  dt.jumptab.emplace(key, d);
+  *out = d;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 dd_plan::~dd_plan() {
@@ -326,6 +441,7 @@ dd_plan::~dd_plan() {
     for (auto& t : kv.second.aoff) (void)hipFree(t.second);
     for (auto& t : kv.second.ralign) (void)hipFree(t.second);
     for (auto& t : kv.second.wintab) (void)hipFree(t.second);
+    for (auto& t : kv.second.jumptab) (void)hipFree(t.second);
     (void)hipSetDevice(cur);
   }
 }

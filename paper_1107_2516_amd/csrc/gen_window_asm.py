@@ -324,11 +324,136 @@ def gen_pairs(name, dw, k, wmax, occ):
     return "\n".join(out)
 
 
+THREAD_CONFIGS = [
+    # threaded-jump flavour: name, DMs per wave, samples per lane, window, waves per SIMD
+    ("t_f32_d8_k12_w48", 8, 12, 48, 3),
+    ("t_f32_d8_k16_w56", 8, 16, 56, 2),
+    ("t_f32_d4_k24_w48", 4, 24, 48, 3),
+]
+
+# fixed SGPRs of the threaded blocks: the block table's address and the jump target
+TPC, TTG = 88, 90
+
+
+def thread_layout(dw, k, wmax):
+    """Byte layout of the threaded block table (shared with the host table
+    builder through the generated constants): DW*NP plain blocks of PBS bytes,
+    then DW*4 reload blocks of RBS bytes.
+
+    plain block (j, o):  K v_add_f32_e32 (4 B each) reading window registers
+                         o .. o+K-1, then the jump to DM j+1's block:
+                         s_add_u32, s_addc_u32, s_setpc_b64 (4 B each); the
+                         last DM's blocks end with s_branch to the exit and
+                         two never-executed s_nop instead
+    reload block (j, q): s_lshl_b32 + v_add_u32_e32 (LDS address of the
+                         window start), WMAX/4 ds_read_b128 (8 B each),
+                         s_waitcnt, then on DM 0 the scalar load of the next
+                         channel's entries (8 B) or two s_nop elsewhere, then
+                         K adds reading registers q .. q+K-1 and the jump."""
+    np_ = wmax - k + 1
+    pbs = 4 * k + 12
+    rbs = 8 + 8 * (wmax // 4) + 4 + 8 + 4 * k + 12
+    return np_, pbs, rbs
+
+
+def gen_thread(name, dw, k, wmax, occ):
+    """Threaded-jump flavour of the register-window step: no VGPR-relative
+    addressing.  Each DM's table entry is the byte offset (within this step's
+    block table) of a block of K plain adds whose window offset is fixed in
+    the code; each block ends by jumping straight to the next DM's block, so a
+    channel costs one computed jump per DM.  A DM whose run lies outside the
+    current window takes a reload block, which loads the window at the DM's
+    own start (entries DW..2DW-1 of the channel, in samples, a multiple of 4)
+    and adds at sub-offset q = shift - start.  DM 0 always reloads.  The host
+    builds and checks every entry (plan_jumptab); an offset outside the table
+    would be a jump into arbitrary code, so the table is validated before it
+    is uploaded."""
+    assert k % 4 == 0 and wmax % 4 == 0 and wmax >= k + 4 and dw in (4, 8)
+    wb = vgpr_budget(occ) - wmax
+    np_, pbs, rbs = thread_layout(dw, k, wmax)
+    nload = "s_load_dwordx8" if dw == 4 else "s_load_dwordx16"
+    vec = "int8v" if dw == 4 else "int16v"
+    out = []
+    out.append(f"// {name}: DW={dw} K={k} WMAX={wmax} OCC={occ}, window v{wb}..v{wb + wmax - 1}, "
+               f"{dw * np_} plain blocks of {pbs} B, {dw * 4} reload blocks of {rbs} B")
+    up = name.upper()
+    out.append(f"#define DD_{up}_NP {np_}")
+    out.append(f"#define DD_{up}_PBS {pbs}")
+    out.append(f"#define DD_{up}_RBS {rbs}")
+    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* e, unsigned addr, const int32_t* next, int* en) {{")
+    out += ["  unsigned va;", f"  {vec} nv;"]
+    out.append("  asm volatile(")
+    out.append(f'      "s_getpc_b64 s[{TPC}:{TPC + 1}]\\n"')
+    out.append('      ".Lpc%=:\\n"')
+    out.append(f'      "s_add_u32 s{TPC}, s{TPC}, .Ltab%=-.Lpc%=\\n"')
+    out.append(f'      "s_addc_u32 s{TPC + 1}, s{TPC + 1}, 0\\n"')
+    out.append(f'      "s_add_u32 s{TTG}, s{TPC}, %[o0]\\n"')
+    out.append(f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"')
+    out.append(f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"')
+    out.append('      ".p2align 6\\n"')
+    out.append('      ".Ltab%=:\\n"')
+
+    def tail(j):
+        if j < dw - 1:
+            return [f'      "s_add_u32 s{TTG}, s{TPC}, %[o{j + 1}]\\n"',
+                    f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"',
+                    f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"']
+        return ['      "s_branch .Lend%=\\n"', '      "s_nop 0\\n"', '      "s_nop 0\\n"']
+
+    def adds(j, o):
+        return [f'      "v_add_f32_e32 %[a{j}_{i}], v{wb + o + i}, %[a{j}_{i}]\\n"' for i in range(k)]
+
+    def place(label, off):
+        return [f'      "{label}:\\n"',
+                f'      ".if ({label}-.Ltab%=) != {off}\\n .error \\"block table misplaced\\"\\n .endif\\n"']
+
+    for j in range(dw):
+        for o in range(np_):
+            out += place(f".Lp%=_{j}_{o}", (j * np_ + o) * pbs)
+            out += adds(j, o)
+            out += tail(j)
+    base = dw * np_ * pbs
+    for j in range(dw):
+        for q in range(4):
+            out += place(f".Lr%=_{j}_{q}", base + (j * 4 + q) * rbs)
+            out.append(f'      "s_lshl_b32 s{TTG}, %[s{j}], 2\\n"')
+            out.append(f'      "v_add_u32_e32 %[va], s{TTG}, %[addr]\\n"')
+            for i in range(wmax // 4):
+                off = f" offset:{16 * i}" if i else ""
+                out.append(f'      "ds_read_b128 v[{wb + 4 * i}:{wb + 4 * i + 3}], %[va]{off}\\n"')
+            out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+            if j == 0:
+                out.append(f'      "{nload} %[rn], %[tp], 0\\n"')
+            else:
+                out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
+            out += adds(j, q)
+            out += tail(j)
+    out.append('      ".Lend%=:\\n"')
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+    outs = []
+    for j in range(dw):
+        for kk in range(k):
+            outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
+    outs += ['[va] "=&v"(va)', '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)']
+    ins += [f'[o{j}] "s"(e[{j}])' for j in range(dw)]
+    ins += [f'[s{j}] "s"(e[{dw + j}])' for j in range(dw)]
+    clob = [f'"v{wb + i}"' for i in range(wmax)]
+    clob += [f'"s{i}"' for i in (TPC, TPC + 1, TTG, TTG + 1)] + ['"scc"', '"memory"']
+    out.append("      : " + ",\n        ".join(outs))
+    out.append("      : " + ", ".join(ins))
+    out.append("      : " + ", ".join(clob) + ");")
+    out.append(f"  for (int i = 0; i < {2 * dw}; i++) en[i] = nv[i];")
+    out.append("}")
+    return "\n".join(out)
+
+
 def main():
     print("// Generated by gen_window_asm.py; do not edit by hand.")
     print("#pragma once")
     print("typedef int int4v __attribute__((ext_vector_type(4)));")
     print("typedef int int8v __attribute__((ext_vector_type(8)));")
+    print("typedef int int16v __attribute__((ext_vector_type(16)));")
     for cfg in CONFIGS:
         print(gen(*cfg))
         print()
@@ -340,6 +465,9 @@ def main():
         print()
     for cfg in PAIR_CONFIGS:
         print(gen_pairs(*cfg))
+        print()
+    for cfg in THREAD_CONFIGS:
+        print(gen_thread(*cfg))
         print()
 
 
