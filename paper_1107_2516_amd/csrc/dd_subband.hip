@@ -48,7 +48,18 @@ struct Pass {
 struct dd_subband_plan {
   int32_t nchans = 0, nsub = 0, cps = 0, ndms = 0;
   std::vector<dd::Pass> passes;
+  // Pinned host copy of one call's launch parameters (they are uploaded with
+  // an asynchronous copy, which needs page-locked memory that outlives the
+  // call); a call reuses it only after the previous call's copy has completed.
+  std::mutex mu;
+  unsigned char* h_params = nullptr;
+  size_t h_params_bytes = 0;
+  hipEvent_t copied = nullptr;  // recorded after the latest parameter upload
+  int device = 0;
   ~dd_subband_plan() {
+    if (copied) (void)hipEventSynchronize(copied);
+    if (copied) (void)hipEventDestroy(copied);
+    if (h_params) (void)hipHostFree(h_params);
     for (auto& ps : passes) {
       for (dd_plan* q : ps.stage1) dd_plan_destroy(q);
       for (dd_plan* q : ps.stage2)
@@ -234,12 +245,15 @@ dd_status dd_subband_sizes(const dd_subband_plan* sp, int64_t nsamp, int64_t* no
   return DD_OK;
 }
 
-dd_status dd_subband_execute(const dd_subband_plan* sp, const float* d_in, int64_t nsamp,
+dd_status dd_subband_execute(const dd_subband_plan* csp, const float* d_in, int64_t nsamp,
                              int64_t in_stride, float* d_out, int64_t out_stride, void* d_workspace,
                              size_t workspace_bytes, void* stream) {
   try {
-    if (!sp || !d_in || !d_out || !d_workspace)
+    if (!csp || !d_in || !d_out || !d_workspace)
       return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
+    // only the pinned parameter staging changes
+    dd_subband_plan* sp = const_cast<dd_subband_plan*>(csp);
+    std::lock_guard<std::mutex> lk(sp->mu);
     if (in_stride < nsamp) return dd::set_error(DD_ERR_INVALID_ARG, "in_stride < nsamp");
     std::vector<int64_t> nout(sp->passes.size());
     size_t need = 0;
@@ -259,7 +273,31 @@ dd_status dd_subband_execute(const dd_subband_plan* sp, const float* d_in, int64
       size_t off = 0;  // parameter array offset from pbase; prefix sums follow
     };
     std::vector<Stage> stages;
-    std::vector<unsigned char> host(params_workspace(sp) - 256, 0);
+    const size_t host_bytes = params_workspace(sp) - 256;
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev));
+    if (sp->copied) {
+      // the previous call's upload reads the pinned buffer until it completes
+      DD_HIP(hipEventSynchronize(sp->copied));
+      if (dev != sp->device) {
+        (void)hipEventDestroy(sp->copied);
+        sp->copied = nullptr;
+      }
+    }
+    if (!sp->copied) {
+      DD_HIP(hipEventCreateWithFlags(&sp->copied, hipEventDisableTiming));
+      sp->device = dev;
+    }
+    if (sp->h_params_bytes < host_bytes) {
+      if (sp->h_params) DD_HIP(hipHostFree(sp->h_params));
+      sp->h_params = nullptr;
+      sp->h_params_bytes = 0;
+      DD_HIP(hipHostMalloc(reinterpret_cast<void**>(&sp->h_params), host_bytes,
+                           hipHostMallocDefault));
+      sp->h_params_bytes = host_bytes;
+    }
+    unsigned char* host = sp->h_params;
+    std::memset(host, 0, host_bytes);
     size_t off = 0;
     auto prepare = [&](std::vector<dd::ExecArgs>& items, int rows) -> dd_status {
       Stage st;
@@ -269,8 +307,8 @@ dd_status dd_subband_execute(const dd_subband_plan* sp, const float* d_in, int64
         r = dd::batch_prepare(dd::default_shape(DD_F32, items[0].plan), DD_F32, items.data(), n, &st.bl);
       if (r != DD_OK) return r;
       st.off = off;
-      std::memcpy(host.data() + off, st.bl.params.data(), st.bl.params.size());
-      std::memcpy(host.data() + off + round256(st.bl.params.size()), st.bl.first_item.data(),
+      std::memcpy(host + off, st.bl.params.data(), st.bl.params.size());
+      std::memcpy(host + off + round256(st.bl.params.size()), st.bl.first_item.data(),
                   st.bl.first_item.size() * 4);
       off += param_area(n);
       stages.push_back(std::move(st));
@@ -311,8 +349,9 @@ dd_status dd_subband_execute(const dd_subband_plan* sp, const float* d_in, int64
       st = prepare(it2, rows2);
       if (st != DD_OK) return st;
     }
-    DD_HIP(hipMemcpyAsync(pbase, host.data(), off, hipMemcpyHostToDevice, s));
-    unsigned* counters = reinterpret_cast<unsigned*>(pbase + host.size());
+    DD_HIP(hipMemcpyAsync(pbase, host, off, hipMemcpyHostToDevice, s));
+    DD_HIP(hipEventRecord(sp->copied, s));
+    unsigned* counters = reinterpret_cast<unsigned*>(pbase + host_bytes);
     for (size_t ip = 0; ip < sp->passes.size(); ip++) {
       const dd::Pass& ps = sp->passes[ip];
       if (ps.p.bin > 1) {
