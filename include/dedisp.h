@@ -115,9 +115,23 @@ dd_status dd_plan_destroy(dd_plan* plan);
  *   d_out device, out_t elements, ndms rows of out_stride (>= nout) elements;
  *         elements t >= nout of each row are not written.
  * Errors: DD_ERR_INVALID_ARG (NULL pointers, strides), DD_ERR_DTYPE (type
- * pair), DD_ERR_NSAMP (nsamp <= max_shift), DD_ERR_HIP (launch failure).
- * FP32 results are summed in FP32 in channel blocks (see DESIGN notes in the
- * repository); 8-bit results are exact.
+ * pair), DD_ERR_NSAMP (nsamp <= max_shift), DD_ERR_TOO_LARGE (the shift
+ * spread of 32 neighbouring DMs of the plan at one channel, plus one time
+ * tile, does not fit a workgroup's 160 KB of LDS even for the LDS-streaming
+ * kernel: about 40000 samples for FP32 input, twice that for f16 and four
+ * times for 8-bit; only very coarse DM grids at low frequencies reach it),
+ * DD_ERR_HIP (launch failure).
+ * Accuracy.  8-bit input gives exact int32 sums.  Float input (f32, or f16
+ * converted exactly to FP32) is summed in FP32 one channel at a time in
+ * channel order 0..nchans-1, so every kernel variant, batch and serving path
+ * gives bit-identical FP32 results for one input, and the error against the
+ * exact sum obeys the recursive-summation bound
+ *     |y - y*| <= (nchans - 1) 2^-24 sum_c |x_c|      (first order),
+ * i.e. a scaled error of at most 6.1e-5 at 1024 channels and 1.2e-4 at 2048.
+ * Realised errors are far smaller: ~2e-7 on zero-mean noise and ~2e-6 on
+ * noise with a large positive offset; the worst inputs found, constant
+ * positive values whose every partial sum rounds the same way, reach
+ * 1.5e-5 at 1024 and 3.1e-5 at 2048 channels.
  */
 dd_status dd_execute(const dd_plan* plan, const void* d_in, dd_dtype in_t, int64_t nsamp,
                      int64_t in_stride, void* d_out, dd_dtype out_t, int64_t out_stride,
