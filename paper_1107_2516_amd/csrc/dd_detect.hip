@@ -99,9 +99,12 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
   const double sg = stats[2 * d + 1];
   if (!(sg > 0.0)) return;  // the whole workgroup: no events in a flat row
   const T* row = in + static_cast<int64_t>(d) * stride;
-  // samples are centred in FP32: x - mu rounded once more than in FP64, far
-  // below the resolution of the S/N threshold test
-  const float muf = static_cast<float>(mu);
+  // samples are centred in FP32 against mu split into two floats,
+  // (x - mu_hi) - mu_lo: within about one rounding of x - mu even where mu's
+  // own FP32 rounding would be a visible bias (8-bit sums near 2^17, whose
+  // FP32 spacing is 1/64 against sigma of a few hundred)
+  const float mu_hi = static_cast<float>(mu);
+  const float mu_lo = static_cast<float>(mu - static_cast<double>(mu_hi));
   // 1 / (sigma sqrt(w)) for w = 1, 2, ..., 64: one lane each, shared through LDS
   // and the prefilter thresholds: every box whose exact S/N test passes
   // (box * inv rounded to FP32 >= nsigma) is >= nsigma / inv less a relative
@@ -130,12 +133,12 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
 #pragma unroll
     for (int u = 0; u < NL; u++) {
       const int i = threadIdx.x + u * kThreads;
-      if (i < kStage) y[padded(i)] = static_cast<float>(v[u]) - muf;
+      if (i < kStage) y[padded(i)] = (static_cast<float>(v[u]) - mu_hi) - mu_lo;
     }
   } else {
     for (int i = threadIdx.x; i < kStage; i += kThreads) {
       const int64_t t = t0 + i;
-      y[padded(i)] = t < nout ? static_cast<float>(row[t]) - muf : 0.f;
+      y[padded(i)] = t < nout ? (static_cast<float>(row[t]) - mu_hi) - mu_lo : 0.f;
     }
   }
   __syncthreads();

@@ -290,6 +290,10 @@ struct BodyWin {
   static constexpr int table_epd = 0;
   // variant 5: the step reads host-scheduled window entries (plan_wintab)
   static constexpr int table_win = SCHED ? WMAX - K : 0;
+  // a window start lies inside the staged slot, and geometry() admits no slot
+  // of 2^14 floats or more (two buffers share 160 KB / OCC), so every start
+  // fits the schedule entry's 14 bits
+  static_assert(!SCHED || 160 * 1024 / OCC_ / 2 / 4 < (1 << 14), "window starts exceed 14 bits");
   // variant 6: the step reads threaded-jump entries (plan_jumptab)
   static constexpr JumpLayout table_jump = JUMP ? jump_layout(DW, K, WMAX) : JumpLayout{};
 };
@@ -816,8 +820,8 @@ struct BodyWinX {
                     jump_layout(DW, K, W).rbs == DD_##NAME##_RBS,         \
                 "jump-table layout differs from the generated blocks");
 DD_CHECK_LAYOUT(T_F32_D8_K12_W48, 8, 12, 48)
-DD_CHECK_LAYOUT(T_F32_D8_K16_W56, 8, 16, 56)
-DD_CHECK_LAYOUT(T_F32_D4_K24_W48, 4, 24, 48)
+DD_CHECK_LAYOUT(T_F32_D8_K20_W56, 8, 20, 56)
+DD_CHECK_LAYOUT(T_F32_D4_K20_W56, 4, 20, 56)
 #undef DD_CHECK_LAYOUT
 
 // ------------------------------------------------------------------ kernels
@@ -982,11 +986,11 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
     if (d == 8 && k == 12)
       return *out = make_impl<BodyWin<8, 12, 48, 3, dd_t_f32_d8_k12_w48_channel, false, true>,
                               float>(), true;
-    if (d == 8 && k == 16)
-      return *out = make_impl<BodyWin<8, 16, 56, 2, dd_t_f32_d8_k16_w56_channel, false, true>,
+    if (d == 8 && k == 20)
+      return *out = make_impl<BodyWin<8, 20, 56, 2, dd_t_f32_d8_k20_w56_channel, false, true>,
                               float>(), true;
-    if (d == 4 && k == 24)
-      return *out = make_impl<BodyWin<4, 24, 48, 3, dd_t_f32_d4_k24_w48_channel, false, true>,
+    if (d == 4 && k == 20)
+      return *out = make_impl<BodyWin<4, 20, 56, 3, dd_t_f32_d4_k20_w56_channel, false, true>,
                               float>(), true;
   }
   if (in_t == DD_F32 && v == 2) {
@@ -1075,16 +1079,9 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
     st = plan_jumptab(a.plan, impl.td, impl.table_jump, &tab);
     if (st != DD_OK) return st;
   } else if (impl.table_win) {
+    // window starts are below the slot, which geometry() has just bounded
+    // below the schedule's 14 bits (static_assert in BodyWin)
     st = plan_wintab(a.plan, impl.td, impl.td / 4, impl.table_win, &tab);
-    if (st == DD_ERR_TOO_LARGE) {
-      // window starts beyond the schedule's 14 bits: the same tile with the
-      // run-time window logic (same body parameters, so the same geometry)
-      TileShape s1 = s;
-      s1.variant = 1;
-      if (!find_impl(s1, in_t, &impl)) return st;
-      tab = tt->d_rel;
-      st = DD_OK;
-    }
     if (st != DD_OK) return st;
   }
   const int64_t n_ttiles = (a.nout + impl.tt - 1) / impl.tt;

@@ -327,8 +327,8 @@ def gen_pairs(name, dw, k, wmax, occ):
 THREAD_CONFIGS = [
     # threaded-jump flavour: name, DMs per wave, samples per lane, window, waves per SIMD
     ("t_f32_d8_k12_w48", 8, 12, 48, 3),
-    ("t_f32_d8_k16_w56", 8, 16, 56, 2),
-    ("t_f32_d4_k24_w48", 4, 24, 48, 3),
+    ("t_f32_d8_k20_w56", 8, 20, 56, 2),
+    ("t_f32_d4_k20_w56", 4, 20, 56, 3),
 ]
 
 # fixed SGPRs of the threaded blocks: the block table's address and the jump target

@@ -139,30 +139,44 @@ def test_batch_autotune_keeps_results():
         assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t))
 
 
-def test_batch_workload_subset_sampled_rows():
-    """Six beams of the many-beam workload (1214-1510 MHz, 64 us, nchans in
-    {256, 512, 1024}, up to 4096 DMs), 8-bit noise; sampled DM rows checked
-    in full against the oracle."""
-    specs = synth.batch_beams()[:6]
-    plans, xs, items = [], [], []
-    for sp in specs:
+def test_batch_workload_all_beams_sampled_rows():
+    """All 32 beams of the many-beam workload (1214-1510 MHz, 64 us, nchans in
+    {256, 512, 1024}, 2^16-2^18 samples, up to 4096 DMs), 8-bit noise with
+    rows pitched to 64 bytes as the benchmark lays them out, in one launch
+    with the autotuned shape; the first, middle and last DM rows and one
+    seeded random row of every beam checked in full against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synth.batch_beams()
+    assert len(specs) == 32
+
+    def gen(sp):
+        return synth.quantize_u8(synth.noise(sp["band"].nchans, sp["nsamp"], sp["seed"]))
+
+    with ThreadPoolExecutor(8) as ex:
+        hosts = list(ex.map(gen, specs))
+    plans, items = [], []
+    for sp, x in zip(specs, hosts):
         bd = sp["band"]
-        dms = synth.dm_grid(sp["ndms"], sp["step"])
-        p = dd.Plan(bd.nchans, bd.f_top, bd.df, bd.t_samp, dms)
-        x = synth.quantize_u8(synth.noise(bd.nchans, sp["nsamp"], sp["seed"]))
+        p = dd.Plan(bd.nchans, bd.f_top, bd.df, bd.t_samp, synth.dm_grid(sp["ndms"], sp["step"]))
+        pitch = (x.shape[1] + 63) // 64 * 64
+        buf = torch.zeros((x.shape[0], pitch), dtype=torch.uint8, device="cuda")
+        buf[:, :x.shape[1]].copy_(torch.from_numpy(x))
         plans.append(p)
-        xs.append(x)
-        items.append((p, torch.from_numpy(x).cuda(), None))
+        items.append((p, buf[:, :x.shape[1]], None))
     b = dd.Batch(items)
+    b.autotune()
     b.launch()
     torch.cuda.synchronize()
-    for sp, p, x, o in zip(specs, plans, xs, b.outputs):
+    g = np.random.default_rng(2517)
+    for i, (sp, p, x, o) in enumerate(zip(specs, plans, hosts, b.outputs)):
         bd = sp["band"]
         tab = oracle.delay_table(bd.nchans, bd.f_top, bd.df, bd.t_samp,
                                  synth.dm_grid(sp["ndms"], sp["step"]))
-        rows = [0, p.ndms // 3, p.ndms - 1]
+        rows = sorted({0, p.ndms // 2, p.ndms - 1, int(g.integers(0, p.ndms))})
         ref = oracle.dedisperse(x, tab, rows=rows)
-        assert np.array_equal(o[rows].cpu().numpy().astype(np.int64), ref)
+        assert np.array_equal(o[rows].cpu().numpy().astype(np.int64), ref), (i, rows)
+    del b, items
+    torch.cuda.empty_cache()
 
 
 def test_batch_set_tile_every_u8_shape():

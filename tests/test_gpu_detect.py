@@ -13,7 +13,7 @@ import paper_1107_2516_amd as dd
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-EPS = 2e-3
+EPS = 1e-4
 
 
 def _check(ev, x, nsigma, kmax, total=None):

@@ -230,8 +230,8 @@ TILES_F32 = [
     dict(variant=5, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=8),
     dict(variant=5, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
     dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
-    dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=6),
-    dict(variant=6, dms_per_wave=4, waves=4, tsamp_per_lane=24, chans_per_stage=4),
+    dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
+    dict(variant=6, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
 ]
 TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}".format(**t) for t in TILES_F32]
 
@@ -269,7 +269,7 @@ def test_threaded_jump_equals_indexed_window(order):
     xt = torch.from_numpy(x).cuda()
     ref = plan.execute_tiled(xt, dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12,
                                       chans_per_stage=8))
-    for k, dw in [(12, 8), (16, 8), (24, 4)]:
+    for k, dw in [(12, 8), (20, 8), (20, 4)]:
         y = plan.execute_tiled(xt, dict(variant=6, dms_per_wave=dw, waves=4, tsamp_per_lane=k,
                                         chans_per_stage=8))
         torch.cuda.synchronize()

@@ -1,13 +1,13 @@
 """GPU parity at the full 1024-channel size: 2^18 samples, 2048 DM trials
 0-1023.5 step 0.5, 20 injected pulses, run in the launch configuration the
-benchmark times.  The oracle recomputes sampled DM rows in full (every row of
-the pulses, the first and last rows and a spread of others); every pulse is
-recovered within one trial with at least half its injected S/N.
+benchmark times.  The oracle recomputes every one of the 2048 DM rows in full
+(in blocks of rows, on all host threads) for the FP32 and 8-bit forms; every
+pulse is recovered within one trial with at least half its injected S/N.
 
-The 8-bit and half-precision forms of the same data follow the same path:
-8-bit bit-exact on the sampled rows; half precision within the FP tolerance
-of the FP64 oracle evaluated on the half values (its distance from the FP32
-data is quantisation, reported and not thresholded).
+The half-precision form is compared on sampled rows (every row of the
+pulses, the first and last rows and a spread of others) within the FP
+tolerance of the FP64 oracle evaluated on the half values (its distance from
+the FP32 data is quantisation, reported and not thresholded).
 """
 import numpy as np
 import pytest
@@ -46,16 +46,20 @@ def _execute(w, x):
     return plan, y
 
 
-def test_scale_f32_sampled_rows_and_pulses(scale_data):
+BLOCK = 256  # DM rows per oracle call (bounds host memory to ~0.5 GB per array)
+
+
+def test_scale_f32_all_rows_and_pulses(scale_data):
     w, tab, x, pulses, rows = scale_data
     plan, y = _execute(w, x)
     assert tuple(y.shape) == (2048, w.nsamp - 15903)
-    ys = y[rows].cpu().numpy()
-    e, _ = scaled_error(ys, x, tab, rows=rows)
-    print(f"scale f32 scaled error {e:.3e} over rows {len(rows)}")
-    assert e <= FP_TOL
-    # the full output is finite everywhere
-    assert bool(torch.isfinite(y).all())
+    worst = 0.0
+    for lo in range(0, 2048, BLOCK):
+        blk = list(range(lo, lo + BLOCK))
+        e, _ = scaled_error(y[lo:lo + BLOCK].cpu().numpy(), x, tab, rows=blk)
+        worst = max(worst, e)
+    print(f"scale f32 scaled error {worst:.3e} over all 2048 rows")
+    assert worst <= FP_TOL
     for p in pulses:
         d0 = int(np.argmin(np.abs(w.dms - p["dm"])))
         lo, hi = max(0, d0 - 2), min(2048, d0 + 3)
@@ -67,14 +71,16 @@ def test_scale_f32_sampled_rows_and_pulses(scale_data):
         assert s[best[0], t_lo + best[1]] >= 0.5 * p["snr"], p
 
 
-def test_scale_u8_bit_exact_sampled_rows(scale_data):
+def test_scale_u8_bit_exact_all_rows(scale_data):
     w, tab, x, pulses, rows = scale_data
     xq = synth.quantize_u8(x)
     plan, y = _execute(w, xq)
     assert y.dtype == torch.int32
-    ys = y[rows].cpu().numpy().astype(np.int64)
-    ref = oracle.dedisperse(xq, tab, rows=rows)
-    assert np.array_equal(ys, ref)
+    for lo in range(0, 2048, BLOCK):
+        ys = y[lo:lo + BLOCK].cpu().numpy().astype(np.int64)
+        ref = oracle.dedisperse(xq, tab, rows=list(range(lo, lo + BLOCK)))
+        bad = np.argwhere(ys != ref)
+        assert bad.size == 0, f"first mismatch at row {lo + bad[0][0]}, t {bad[0][1]}"
 
 
 def test_scale_f16_sampled_rows(scale_data):

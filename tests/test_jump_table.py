@@ -18,7 +18,7 @@ import oracle
 import paper_1107_2516_amd as dd
 import synth
 
-SHAPES = [(8, 12, 48), (8, 16, 56), (4, 24, 48)]
+SHAPES = [(8, 12, 48), (8, 20, 56), (4, 20, 56)]
 
 
 def layout(dw, k, wmax):
