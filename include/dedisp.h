@@ -346,6 +346,21 @@ dd_status dd_detect(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nou
                     int64_t out_stride, float nsigma, int32_t max_log2_width, double* d_stats,
                     dd_event* d_events, int64_t max_events, uint64_t* d_count, void* stream);
 
+/*
+ * For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): dd_detect without the d_stats
+ * buffer.  The per-row statistics live in a static device array of the
+ * library (65535 rows, 1 MB, one per GPU, held until the process ends); this
+ * call allocates nothing.  Other arguments, results and errors as dd_detect;
+ * ndms > 65535 returns DD_ERR_TOO_LARGE.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams, no
+ * ordering between them) race on it and must be serialised by the caller.
+ */
+dd_status dd_detect_noalloc(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nout,
+                            int64_t out_stride, float nsigma, int32_t max_log2_width,
+                            dd_event* d_events, int64_t max_events, uint64_t* d_count,
+                            void* stream);
+
 /* ------------------------------------------------------------ subband
  *
  * Section 3.2's approximate method for large DM ranges, as a survey plan of

@@ -110,6 +110,8 @@ _SIGS = {
     "dd_serve_stats": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                        ctypes.POINTER(ctypes.c_size_t)],
     "dd_detect": [_P, ctypes.c_int, _I32, _I64, _I64, ctypes.c_float, _I32, _P, _P, _I64, _P, _P],
+    "dd_detect_noalloc": [_P, ctypes.c_int, _I32, _I64, _I64, ctypes.c_float, _I32, _P, _I64, _P,
+                          _P],
     "dd_corner_turn": [_P, ctypes.c_int, _I64, _I32, _I64, _I32, _P, _I64, _P],
     "dd_channelise": [_P, _I64, _I32, _I64, _I32, _P, _I64, _P],
     "dd_subband_plan_create": [_I32, _D, _D, _D, _I32, _P, _I32, _PP],
@@ -492,6 +494,31 @@ def detect(out, nsigma, max_log2_width=6, max_events=1 << 20, stream=None):
     host = ev[:k].cpu().numpy().reshape(-1).view(EVENT_DTYPE)
     host = host[np.lexsort((host["t"], host["dm_row"]))]
     return host, stats, n
+
+
+def detect_noalloc(out, nsigma, events, count, max_log2_width=6, stream=None):
+    """dd_detect_noalloc: detection into caller tensors `events` (uint8
+    [max_events, 24]) and `count` (int64 [1]) on the device, with the per-row
+    statistics in the library's static device array; queues the work on
+    `stream` and returns without waiting or allocating."""
+    if out.dim() != 2 or out.stride(1) != 1:
+        raise DedispError(DD_ERR_INVALID_ARG, "out must be [ndms, nout] with contiguous rows")
+    if events.dim() != 2 or events.shape[1] != EVENT_DTYPE.itemsize or not events.is_contiguous():
+        raise DedispError(DD_ERR_INVALID_ARG, "events must be contiguous [max_events, 24] bytes")
+    ndms, nout = out.shape
+    _check(lib().dd_detect_noalloc(out.data_ptr(), dtype_code(out.dtype), ndms, nout,
+                                   out.stride(0), float(nsigma), int(max_log2_width),
+                                   events.data_ptr(), int(events.shape[0]), count.data_ptr(),
+                                   stream_handle(stream)))
+
+
+def events_from_device(events, count):
+    """Host copy of the first min(count, capacity) events, sorted by (dm_row, t),
+    and the total count."""
+    n = int(count.item())
+    k = min(n, events.shape[0])
+    host = events[:k].cpu().numpy().reshape(-1).view(EVENT_DTYPE)
+    return host[np.lexsort((host["t"], host["dm_row"]))], n
 
 
 def corner_turn(spectra, flip=False, out=None, stream=None):

@@ -16,6 +16,9 @@
 //     computes the exact S/N, so the events are those of the exact test
 //     alone.  Events are appended with one 64-bit atomic per wavefront and
 //     sample slot.
+#include <map>
+#include <mutex>
+
 #include "dd_internal.h"
 
 namespace dd {
@@ -231,6 +234,35 @@ __global__ __launch_bounds__(kThreads) void k_boxcar(const T* __restrict__ in, i
 
 __global__ void k_clear_count(unsigned long long* count) { *count = 0ull; }
 
+// dd_detect_noalloc keeps the per-row statistics (mu_d, sigma_d) in this
+// array instead of a caller buffer: each GPU the library runs on holds its
+// own copy (1 MB) until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns, once
+// per device.  k_row_stats writes every row before k_boxcar reads it, so
+// nothing in the array has to start at zero.
+constexpr int kScratchRows = 65535;
+static __device__ __align__(256) double scratch[2 * kScratchRows];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;  // device -> address of that device's array
+
+dd_status scratch_address(double** out) {
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return set_error(DD_ERR_HIP, "no device address for the statistics array");
+    it = g_scratch_addr.emplace(dev, static_cast<double*>(p)).first;
+  }
+  *out = it->second;
+  return DD_OK;
+}
+
 template <typename T>
 dd_status launch_detect(const T* in, int32_t ndms, int64_t nout, int64_t stride, float nsigma,
                         int kmax, double* stats, dd_event* events, int64_t max_events,
@@ -248,6 +280,25 @@ dd_status launch_detect(const T* in, int32_t ndms, int64_t nout, int64_t stride,
 
 }  // namespace
 }  // namespace dd
+
+extern "C" dd_status dd_detect_noalloc(const void* d_out, dd_dtype out_t, int32_t ndms,
+                                       int64_t nout, int64_t out_stride, float nsigma,
+                                       int32_t max_log2_width, dd_event* d_events,
+                                       int64_t max_events, uint64_t* d_count, void* stream) {
+  try {
+    if (ndms < 1) return dd::set_error(DD_ERR_INVALID_ARG, "bad sizes");
+    if (ndms > dd::kScratchRows)
+      return dd::set_error(DD_ERR_TOO_LARGE,
+                           "more DM rows than the static statistics array holds (65535)");
+    double* stats = nullptr;
+    const dd_status st = dd::scratch_address(&stats);
+    if (st != DD_OK) return st;
+    return dd_detect(d_out, out_t, ndms, nout, out_stride, nsigma, max_log2_width, stats,
+                     d_events, max_events, d_count, stream);
+  } catch (...) {
+    return dd::set_error(DD_ERR_INVALID_ARG, "unexpected C++ exception");
+  }
+}
 
 extern "C" dd_status dd_detect(const void* d_out, dd_dtype out_t, int32_t ndms, int64_t nout,
                                int64_t out_stride, float nsigma, int32_t max_log2_width,
