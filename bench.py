@@ -228,6 +228,38 @@ def run_single(dd, torch, plan, w, xh, dt, args):
             "real_time_factor": (kms * 1e-3) / (nout * w.band.t_samp)}, out
 
 
+def run_copies(torch, xh, out, reps=3):
+    """Host<->device copies of one step's input and output through pinned
+    host memory, timed with HIP events on the current stream.  The paper
+    times its kernel without them and reports them per stage (section 4;
+    section 5, Table 6); they are never part of `value`."""
+    dev = out.device
+    stream = torch.cuda.current_stream(dev)
+    hin = torch.from_numpy(xh).pin_memory()
+    din = torch.empty(hin.shape, dtype=hin.dtype, device=dev)
+    hout = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+
+    def one(dst, src):
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize(dev)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            dst.copy_(src, non_blocking=True)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        return a.elapsed_time(b) / reps
+
+    h2d = one(din, hin)
+    d2h = one(hout, out)
+    nin = hin.numel() * hin.element_size()
+    nout = out.numel() * out.element_size()
+    del hin, din, hout
+    return {"h2d_bytes": nin, "h2d_ms": h2d, "h2d_gbs": nin / (h2d * 1e-3) / 1e9,
+            "d2h_bytes": nout, "d2h_ms": d2h, "d2h_gbs": nout / (d2h * 1e-3) / 1e9,
+            "host_memory": "pinned"}
+
+
 def boxcar_snr_peak(row, t0, width, search=64):
     """Peak boxcar S/N of a de-dispersed row near output sample t0, with the
     row's median and 1.4826*MAD as baseline and scale."""
@@ -247,20 +279,13 @@ def pulse_snrs(out, w, pulses):
     return [boxcar_snr_peak(host[i], p["t0"], p["width"]) for i, p in enumerate(pulses)]
 
 
-def cpu_baseline(w, xs, outs, budget_s):
-    """The oracle (plain C, FP64/int64 accumulation, OpenMP over DM rows)
-    timed on a bounded sample of DM rows over the full time range, and the
-    GPU results of every precision compared with it on those rows."""
+def time_oracle_rows(x, tab, threads, budget_s):
+    """Time the oracle on an evenly spread sample of DM rows over the full time
+    range, the row count sized from a probe to take about budget_s.  Returns
+    (DM-trial samples/s, rows, seconds, oracle rows)."""
     import oracle
-    b = w.band
-    tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
     ndms = tab.shape[0]
-    x = xs["f32"]
     nout = x.shape[1] - int(tab.max())
-    threads = len(os.sched_getaffinity(0))
-    env = os.environ.get("OMP_NUM_THREADS")
-    if env and env.isdigit():
-        threads = min(threads, int(env))
     probe = max(threads, 8)
     rows = np.linspace(0, ndms - 1, probe).astype(np.int32)
     t0 = time.perf_counter()
@@ -272,11 +297,47 @@ def cpu_baseline(w, xs, outs, budget_s):
     t0 = time.perf_counter()
     ref = oracle.dedisperse(x, tab, rows=rows, nthreads=threads)
     dt = time.perf_counter() - t0
-    res = {"value": nrows * nout / dt, "unit": "DM-trial samples/s", "cores": threads,
+    return nrows * nout / dt, rows, dt, ref
+
+
+def oracle_threads():
+    threads = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        threads = min(threads, int(env))
+    return threads
+
+
+def cpu_baseline(w, xs, outs, budget_s):
+    """The oracle (plain C, FP64/int64 accumulation, OpenMP over DM rows)
+    timed on a bounded sample of DM rows over the full time range for each
+    precision of the step, and the GPU results of every precision compared
+    with it on those rows."""
+    import oracle
+    b = w.band
+    tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)
+    ndms = tab.shape[0]
+    x = xs["f32"]
+    nout = x.shape[1] - int(tab.max())
+    threads = oracle_threads()
+    rate, rows, dt, ref = time_oracle_rows(x, tab, threads, budget_s)
+    nrows = len(rows)
+    res = {"value": rate, "unit": "DM-trial samples/s", "cores": threads,
            "kind": "oracle",
            "sample": f"{nrows} of {ndms} DM rows x {nout} output samples x {b.nchans} channels "
                      f"({dt:.1f} s on {threads} threads)",
            "cpu_model": cpu_model()}
+    # the other precisions of the same data (8-bit: int64 sums; binary16:
+    # FP64 sums), a third of the budget each
+    per = {}
+    for pdt in ("u8", "f16"):
+        if pdt in xs:
+            r, rr, d, _ = time_oracle_rows(xs[pdt], tab, threads, budget_s / 3)
+            per[pdt] = {"value": r, "unit": "DM-trial samples/s", "cores": threads,
+                        "sample": f"{len(rr)} of {ndms} DM rows x {nout} output samples "
+                                  f"({d:.1f} s on {threads} threads)"}
+    if per:
+        res["precisions"] = per
     # one core, as the paper's CPU baseline: a few rows
     one = rows[:: max(1, nrows // 4)][:4]
     t1 = time.perf_counter()
@@ -571,8 +632,11 @@ def run_batch(dd, torch, args):
 
     log("batch: generating 32 beams")
     xs = []
+    oracle_beams = {}  # host copies of the beams the oracle is timed on
     with ThreadPoolExecutor(8) as ex:
-        for u8 in ex.map(gen, range(len(specs))):
+        for i, u8 in enumerate(ex.map(gen, range(len(specs)))):
+            if i < 2:
+                oracle_beams[i] = u8
             # rows start on 64-byte boundaries (pitched allocation)
             pitch = (u8.shape[1] + 63) // 64 * 64
             buf = torch.empty((u8.shape[0], pitch), dtype=torch.uint8, device=dev)
@@ -601,6 +665,30 @@ def run_batch(dd, torch, args):
            "grid": info["grid"], "tile": info["tile"], "autotune": tuned,
            "unbatched_ms": seq_wall, "speedup_vs_unbatched": seq_wall / wall_ms,
            "roofline": roofline(adds, in_bytes, samples * 4.0, kms, "TOP/s")}
+    if not args.no_cpu_baseline:
+        # the oracle on two of the 32 beams (a sample of DM rows each), its add
+        # rate extrapolated linearly to the whole batch
+        import oracle
+        threads = oracle_threads()
+        t_adds, t_s, parts = 0.0, 0.0, []
+        for i, xh in oracle_beams.items():
+            sp = specs[i]
+            bd = sp["band"]
+            tab = oracle.delay_table(bd.nchans, bd.f_top, bd.df, bd.t_samp,
+                                     synth.dm_grid(sp["ndms"], sp["step"]))
+            _, rows, d, _ = time_oracle_rows(xh, tab, threads, args.cpu_seconds / 4)
+            n_out = xh.shape[1] - int(tab.max())
+            t_adds += float(len(rows)) * bd.nchans * n_out
+            t_s += d
+            parts.append(f"beam {i}: {len(rows)} of {sp['ndms']} DM rows x {n_out} samples x "
+                         f"{bd.nchans} ch")
+        add_rate = t_adds / t_s
+        est_s = adds / add_rate
+        res["cpu_baseline"] = {"value": samples / est_s, "unit": "DM-trial samples/s",
+                               "cores": threads, "kind": "oracle", "extrapolated": True,
+                               "sample": "; ".join(parts) + f" ({t_s:.1f} s); batch time "
+                                         f"extrapolated from the add rate: {est_s:.0f} s",
+                               "gpu_over_cpu": (samples / (wall_ms * 1e-3)) / (samples / est_s)}
     del bt, xs
     torch.cuda.empty_cache()
     return res
@@ -631,10 +719,13 @@ def run_serve(dd, torch, args, nbeams=64):
     g = synth.rng(seed + 2)
     phase = [int(v) for v in g.integers(0, period, nbeams)]
 
-    carry = (m + max_chunk) * band.nchans
+    # per beam a device ring of 2 max_shift + max_chunk (+64) samples per
+    # channel; per chunk in flight its device copy and its output
+    ring = (2 * m + max_chunk + 64) * band.nchans
     out_max = plan.ndms * ((max_chunk + 63) // 64 * 64) * 4
     max_inflight, nstreams = 8, 4
-    arena_bytes = nbeams * carry + nstreams * m * band.nchans + 2 * max_inflight * out_max + (1 << 30)
+    arena_bytes = (nbeams * (ring + 256) + 2 * max_inflight * (out_max + max_chunk * band.nchans)
+                   + (1 << 30))
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     srv = dd.Server(arena, torch.uint8, max_inflight=max_inflight, queue_capacity=512,
                     nstreams=nstreams, host_staging_bytes=4 << 30)
@@ -754,8 +845,28 @@ def run_serve(dd, torch, args, nbeams=64):
     kernel_rate = plan.ndms * max_chunk / (kms * 1e-3)
     adds = float(plan.ndms) * plan.nchans * max_chunk
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on one beam's carry + largest chunk (a sample of DM rows),
+        # extrapolated to the 4096 rows of the chunk
+        import oracle
+        threads = oracle_threads()
+        tab = oracle.delay_table(band.nchans, band.f_top, band.df, band.t_samp,
+                                 synth.dm_grid(4096, 0.125))
+        xo = np.ascontiguousarray(pool[:, :m + max_chunk])
+        rate, rows, d, _ = time_oracle_rows(xo, tab, threads, args.cpu_seconds / 4)
+        chunk_s = plan.ndms * max_chunk / rate
+        cpu = {"value": rate, "unit": "DM-trial samples/s", "cores": threads, "kind": "oracle",
+               "extrapolated": True,
+               "sample": f"{len(rows)} of {plan.ndms} DM rows x {max_chunk} samples x "
+                         f"{band.nchans} ch of one 2^17-sample chunk ({d:.1f} s); whole chunk "
+                         f"extrapolated: {chunk_s:.0f} s",
+               "real_time_factor_64_beams": chunk_s * nbeams / (max_chunk * band.t_samp)}
+        del xo
+
     obs = paced_samples * band.t_samp / nbeams
     return {
+        "cpu_baseline": cpu,
         "beams": nbeams, "nchans": band.nchans, "ndms": plan.ndms, "max_shift": m,
         "tile": tuned_tile,
         "chunk_samples": [1 << 14, max_chunk], "arrival_rate_x_realtime": 1.5,
@@ -866,6 +977,11 @@ def main():
            "tile": main_r["tile"]}
     line = base_line(args, main_r["value"], main_r["ms_per_step"], dt, cfg, main_r["roofline"])
     line["real_time_factor"] = main_r["real_time_factor"]
+    log(f"{name}: host<->device copies")
+    cp = run_copies(torch, xs[dt], main_out)
+    cp["value_with_copies"] = plan.ndms * plan.nout(w.nsamp) / (
+        (cp["h2d_ms"] + main_r["kernel_ms"] + cp["d2h_ms"]) * 1e-3)
+    line["copies"] = cp
     outs = {dt: main_out}
     extras = name == "scale_f32" and not args.only
     if extras:
