@@ -69,8 +69,10 @@ struct DeviceTables {
   std::map<std::pair<int, int>, int32_t*> ralign;
   // scheduled register-window entries, keyed by (td, DMs per wave, slack)
   std::map<std::tuple<int, int, int>, int32_t*> wintab;
-  // threaded-jump entries, keyed by (td, DMs per wave, samples per lane, window)
-  std::map<std::tuple<int, int, int, int>, int32_t*> jumptab;
+  // threaded-jump entries, keyed by (td, DMs per wave, samples per lane,
+  // window, plain and reload block sizes): the entries are byte offsets into
+  // one step's block table, so two layouts never share them
+  std::map<std::tuple<int, int, int, int, int, int>, int32_t*> jumptab;
 };
 
 }  // namespace dd
@@ -126,6 +128,12 @@ struct JumpLayout {
 };
 constexpr JumpLayout jump_layout(int dw, int k, int wmax) {
   return JumpLayout{dw, k, wmax, wmax - k + 1, 4 * k + 12, 8 + 2 * wmax + 4 + 8 + 4 * k + 12};
+}
+// Shared-window flavour (FP32 variant 7): window of 4k samples, plain blocks
+// padded to 8k + 12 bytes (up to k DPP adds of 8 bytes), reload blocks with
+// k/2 window reads and k DPP moves.  Same entries, builder and checker.
+constexpr JumpLayout shared_jump_layout(int dw, int k) {
+  return JumpLayout{dw, k, 4 * k, 3 * k + 1, 8 * k + 12, 8 + 4 * k + 4 + 8 + 8 * k + 4 + 4 * k + 12};
 }
 // Entries for ngroups groups of dw DMs from their shifts rel[g*dw + j]
 // relative to the staged window (>= 0): DM 0 reloads at rel & ~3, a later DM

@@ -40,6 +40,9 @@
 //                  window offset is fixed; each DM's host-built (and
 //                  host-checked) table entry names its block, and every block
 //                  jumps straight to the next DM's (plan_jumptab).
+//  7  BodyWin:     variant 6 with windows shared between neighbouring lanes:
+//                  a lane reads half its window from LDS and takes the rest
+//                  from the next two lanes through DPP wavefront shifts.
 #include <cstring>
 #include <type_traits>
 
@@ -200,11 +203,14 @@ struct BodyLds {
 // SCHED (variant 5): the table holds host-scheduled window entries instead
 // of rel (plan_wintab), for the steps generated by gen_sched; the body is the
 // same.
+// LANES < 64 (variant 7): the register windows of neighbouring lanes are
+// shared through DPP, so the last lanes only supply data and a wave stores
+// LANES * K samples.
 template <int DW, int K, int WMAX, int OCC_,
           void (*STEP)(float*, const int*, unsigned, const int32_t*, int*), bool SCHED = false,
-          bool JUMP = false>
+          bool JUMP = false, int LANES = 64>
 struct BodyWin {
-  static constexpr int TD = 4 * DW, TT = 64 * K, OCC = OCC_;
+  static constexpr int TD = 4 * DW, TT = LANES * K, OCC = OCC_;
   static constexpr int EW = JUMP ? 2 : 1;  // table words per DM and channel
   __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -271,7 +277,7 @@ struct BodyWin {
 #pragma unroll
       for (int k = 0; k < K; k++) {
         const int64_t t = t0 + lane * K + k;
-        if (t < p.nout) o[t] = acc[j * K + k];
+        if (lane < LANES && t < p.nout) o[t] = acc[j * K + k];
       }
     }
   }
@@ -294,8 +300,12 @@ struct BodyWin {
   // of 2^14 floats or more (two buffers share 160 KB / OCC), so every start
   // fits the schedule entry's 14 bits
   static_assert(!SCHED || 160 * 1024 / OCC_ / 2 / 4 < (1 << 14), "window starts exceed 14 bits");
-  // variant 6: the step reads threaded-jump entries (plan_jumptab)
-  static constexpr JumpLayout table_jump = JUMP ? jump_layout(DW, K, WMAX) : JumpLayout{};
+  // variants 6 and 7: the step reads threaded-jump entries (plan_jumptab)
+  static constexpr JumpLayout table_jump = !JUMP       ? JumpLayout{}
+                                           : LANES < 64 ? shared_jump_layout(DW, K)
+                                                        : jump_layout(DW, K, WMAX);
+  static_assert(LANES == 64 || (JUMP && WMAX == 4 * K && LANES == 62),
+                "shared windows: threaded-jump step, window 4K, two supplying lanes");
 };
 
 // ---------------------------------------------------------------- variant 3
@@ -823,6 +833,11 @@ DD_CHECK_LAYOUT(T_F32_D8_K12_W48, 8, 12, 48)
 DD_CHECK_LAYOUT(T_F32_D8_K20_W56, 8, 20, 56)
 DD_CHECK_LAYOUT(T_F32_D4_K20_W56, 4, 20, 56)
 #undef DD_CHECK_LAYOUT
+static_assert(shared_jump_layout(8, 12).np == DD_W_F32_D8_K12_NP &&
+                  shared_jump_layout(8, 12).pbs == DD_W_F32_D8_K12_PBS &&
+                  shared_jump_layout(8, 12).rbs == DD_W_F32_D8_K12_RBS &&
+                  shared_jump_layout(8, 12).wmax == DD_W_F32_D8_K12_WMAX,
+              "shared-window layout differs from the generated blocks");
 
 // ------------------------------------------------------------------ kernels
 
@@ -991,6 +1006,11 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
                               float>(), true;
     if (d == 4 && k == 20)
       return *out = make_impl<BodyWin<4, 20, 56, 3, dd_t_f32_d4_k20_w56_channel, false, true>,
+                              float>(), true;
+  }
+  if (in_t == DD_F32 && v == 7) {
+    if (d == 8 && k == 12)
+      return *out = make_impl<BodyWin<8, 12, 48, 3, dd_w_f32_d8_k12_channel, false, true, 62>,
                               float>(), true;
   }
   if (in_t == DD_F32 && v == 2) {

@@ -382,7 +382,7 @@ dd_status plan_jumptab(dd_plan* plan, int td, const JumpLayout& L, const int32_t
   DD_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(plan->mu);
   DeviceTables& dt = plan->dev[dev];
-  const auto key = std::make_tuple(td, L.dw, L.k, L.wmax);
+  const auto key = std::make_tuple(td, L.dw, L.k, L.wmax, L.pbs, L.rbs);
   auto it = dt.jumptab.find(key);
   if (it != dt.jumptab.end()) {
     *out = it->second;

@@ -448,6 +448,147 @@ def gen_thread(name, dw, k, wmax, occ):
     return "\n".join(out)
 
 
+SHARED_CONFIGS = [
+    # shared-window flavour: name, DMs per wave, samples per lane, waves per SIMD
+    ("w_f32_d8_k12", 8, 12, 3),
+]
+
+
+def shared_layout(dw, k):
+    """Byte layout of the shared-window block table: DW*NP plain blocks of PBS
+    bytes, then DW*4 reload blocks of RBS bytes (window of 4K floats, NP =
+    3K+1 window offsets).
+
+    plain block (j, o):  K adds (o+i < 2K: own registers, 4 B each;
+                         2K <= o+i < 3K: the neighbour's copy, 4 B;
+                         3K <= o+i: DPP from the next lane, 8 B), then the jump
+                         to DM j+1's block (12 B), padded with s_nop to the
+                         largest block (8K + 12 B)
+    reload block (j, q): s_lshl_b32 + v_add_u32_e32, K/2 ds_read_b128,
+                         s_waitcnt, the scalar load of the next channel's
+                         entries on DM 0 (8 B) or two s_nop, K v_mov_b32_dpp
+                         (the next lane's second run), s_nop 1, K adds of
+                         registers q..q+K-1 and the jump"""
+    np_ = 3 * k + 1
+    pbs = 8 * k + 12
+    rbs = 8 + 8 * (k // 2) + 4 + 8 + 8 * k + 4 + 4 * k + 12
+    return np_, pbs, rbs
+
+
+def gen_shared(name, dw, k, occ):
+    """Shared-window flavour of the threaded-jump step.  Lanes' register
+    windows overlap: lane l's window of 4K samples starts K samples after lane
+    l-1's.  Each lane reads only the first 2K samples of its window from LDS
+    (run A); the next K come from lane l+1's second run (A[K..2K-1]) through
+    one DPP wavefront shift (run B, K v_mov_b32_dpp per window load), and the
+    last K from lane l+2, read by the adds themselves as DPP operands on B.
+    A window load thus costs half the LDS bytes of a private one.  Lanes 62
+    and 63 only supply data (their own sums are never stored), so a wave
+    owns 62*K output samples.  Block selection and table as gen_thread; the
+    table builder and checker are shared with it (window 4K, slack 3K)."""
+    assert k % 4 == 0 and dw in (4, 8)
+    wmax = 4 * k
+    # window registers at the top of the budget: A (2K) then B (K)
+    wb = vgpr_budget(occ) - 3 * k
+    va, vb = wb, wb + 2 * k
+    np_, pbs, rbs = shared_layout(dw, k)
+    nload = "s_load_dwordx8" if dw == 4 else "s_load_dwordx16"
+    vec = "int8v" if dw == 4 else "int16v"
+    out = []
+    out.append(f"// {name}: DW={dw} K={k} OCC={occ}, run A v{va}..v{va + 2 * k - 1}, "
+               f"run B v{vb}..v{vb + k - 1}, {dw * np_} plain blocks of {pbs} B, "
+               f"{dw * 4} reload blocks of {rbs} B")
+    up = name.upper()
+    out.append(f"#define DD_{up}_NP {np_}")
+    out.append(f"#define DD_{up}_PBS {pbs}")
+    out.append(f"#define DD_{up}_RBS {rbs}")
+    out.append(f"#define DD_{up}_WMAX {wmax}")
+    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* e, unsigned addr, const int32_t* next, int* en) {{")
+    out += ["  unsigned va;", f"  {vec} nv;"]
+    out.append("  asm volatile(")
+    out.append(f'      "s_getpc_b64 s[{TPC}:{TPC + 1}]\\n"')
+    out.append('      ".Lpc%=:\\n"')
+    out.append(f'      "s_add_u32 s{TPC}, s{TPC}, .Ltab%=-.Lpc%=\\n"')
+    out.append(f'      "s_addc_u32 s{TPC + 1}, s{TPC + 1}, 0\\n"')
+    out.append(f'      "s_add_u32 s{TTG}, s{TPC}, %[o0]\\n"')
+    out.append(f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"')
+    out.append(f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"')
+    out.append('      ".p2align 6\\n"')
+    out.append('      ".Ltab%=:\\n"')
+
+    def tail(j):
+        if j < dw - 1:
+            return [f'      "s_add_u32 s{TTG}, s{TPC}, %[o{j + 1}]\\n"',
+                    f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"',
+                    f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"']
+        return ['      "s_branch .Lend%=\\n"', '      "s_nop 0\\n"', '      "s_nop 0\\n"']
+
+    def add(j, i, w):
+        if w < 2 * k:
+            return f'      "v_add_f32_e32 %[a{j}_{i}], v{va + w}, %[a{j}_{i}]\\n"', 4
+        if w < 3 * k:
+            return f'      "v_add_f32_e32 %[a{j}_{i}], v{vb + w - 2 * k}, %[a{j}_{i}]\\n"', 4
+        return (f'      "v_add_f32_dpp %[a{j}_{i}], v{vb + w - 3 * k}, %[a{j}_{i}] '
+                f'wave_shl:1 row_mask:0xf bank_mask:0xf\\n"', 8)
+
+    def place(label, off):
+        return [f'      "{label}:\\n"',
+                f'      ".if ({label}-.Ltab%=) != {off}\\n .error \\"block table misplaced\\"\\n .endif\\n"']
+
+    for j in range(dw):
+        for o in range(np_):
+            out += place(f".Lp%=_{j}_{o}", (j * np_ + o) * pbs)
+            size = 0
+            for i in range(k):
+                line, n = add(j, i, o + i)
+                out.append(line)
+                size += n
+            out += tail(j)
+            size += 12
+            assert (pbs - size) % 4 == 0
+            out += ['      "s_nop 0\\n"'] * ((pbs - size) // 4)
+    base = dw * np_ * pbs
+    for j in range(dw):
+        for q in range(4):
+            out += place(f".Lr%=_{j}_{q}", base + (j * 4 + q) * rbs)
+            out.append(f'      "s_lshl_b32 s{TTG}, %[s{j}], 2\\n"')
+            out.append(f'      "v_add_u32_e32 %[va], s{TTG}, %[addr]\\n"')
+            for i in range(k // 2):
+                off = f" offset:{16 * i}" if i else ""
+                out.append(f'      "ds_read_b128 v[{va + 4 * i}:{va + 4 * i + 3}], %[va]{off}\\n"')
+            out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+            if j == 0:
+                out.append(f'      "{nload} %[rn], %[tp], 0\\n"')
+            else:
+                out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
+            for m in range(k):
+                out.append(f'      "v_mov_b32_dpp v{vb + m}, v{va + k + m} wave_shl:1 '
+                           f'row_mask:0xf bank_mask:0xf\\n"')
+            # a DPP read of a VGPR written by VALU needs two wait states
+            out.append('      "s_nop 1\\n"')
+            for i in range(k):
+                out.append(add(j, i, q + i)[0])
+            out += tail(j)
+    out.append('      ".Lend%=:\\n"')
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+    outs = []
+    for j in range(dw):
+        for kk in range(k):
+            outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
+    outs += ['[va] "=&v"(va)', '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)']
+    ins += [f'[o{j}] "s"(e[{j}])' for j in range(dw)]
+    ins += [f'[s{j}] "s"(e[{dw + j}])' for j in range(dw)]
+    clob = [f'"v{wb + i}"' for i in range(3 * k)]
+    clob += [f'"s{i}"' for i in (TPC, TPC + 1, TTG, TTG + 1)] + ['"scc"', '"memory"']
+    out.append("      : " + ",\n        ".join(outs))
+    out.append("      : " + ", ".join(ins))
+    out.append("      : " + ", ".join(clob) + ");")
+    out.append(f"  for (int i = 0; i < {2 * dw}; i++) en[i] = nv[i];")
+    out.append("}")
+    return "\n".join(out)
+
+
 def main():
     print("// Generated by gen_window_asm.py; do not edit by hand.")
     print("#pragma once")
@@ -468,6 +609,9 @@ def main():
         print()
     for cfg in THREAD_CONFIGS:
         print(gen_thread(*cfg))
+        print()
+    for cfg in SHARED_CONFIGS:
+        print(gen_shared(*cfg))
         print()
 
 

@@ -232,6 +232,7 @@ TILES_F32 = [
     dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
     dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
     dict(variant=6, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
+    dict(variant=7, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
 ]
 TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}".format(**t) for t in TILES_F32]
 
@@ -255,8 +256,9 @@ def test_f32_kernel_variants(tile, maxd):
 
 @pytest.mark.parametrize("order", ["sorted", "shuffled"])
 def test_threaded_jump_equals_indexed_window(order):
-    """The threaded-jump kernel (plain adds in code blocks chosen through the
-    host table) and the VGPR-indexed window kernel add the same samples in
+    """The threaded-jump kernels (plain adds in code blocks chosen through the
+    host table; variant 7 with windows shared between lanes through DPP) and
+    the VGPR-indexed window kernel add the same samples in
     the same channel order, so their FP32 outputs are identical bit for bit;
     a shuffled DM list makes shifts non-monotone inside a wavefront (many
     window reloads) and leaves a ragged last tile and time tile."""
@@ -269,11 +271,11 @@ def test_threaded_jump_equals_indexed_window(order):
     xt = torch.from_numpy(x).cuda()
     ref = plan.execute_tiled(xt, dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12,
                                       chans_per_stage=8))
-    for k, dw in [(12, 8), (20, 8), (20, 4)]:
-        y = plan.execute_tiled(xt, dict(variant=6, dms_per_wave=dw, waves=4, tsamp_per_lane=k,
+    for v, k, dw in [(6, 12, 8), (6, 20, 8), (6, 20, 4), (7, 12, 8)]:
+        y = plan.execute_tiled(xt, dict(variant=v, dms_per_wave=dw, waves=4, tsamp_per_lane=k,
                                         chans_per_stage=8))
         torch.cuda.synchronize()
-        assert torch.equal(y, ref), (k, dw)
+        assert torch.equal(y, ref), (v, k, dw)
     e, _ = scaled_error(ref.cpu().numpy(), x, tab)
     assert e <= FP_TOL, e
 
