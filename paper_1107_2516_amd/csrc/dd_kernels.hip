@@ -832,12 +832,18 @@ struct BodyWinX {
 DD_CHECK_LAYOUT(T_F32_D8_K12_W48, 8, 12, 48)
 DD_CHECK_LAYOUT(T_F32_D8_K20_W56, 8, 20, 56)
 DD_CHECK_LAYOUT(T_F32_D4_K20_W56, 4, 20, 56)
+DD_CHECK_LAYOUT(T_F32_D4_K12_W48, 4, 12, 48)
 #undef DD_CHECK_LAYOUT
-static_assert(shared_jump_layout(8, 12).np == DD_W_F32_D8_K12_NP &&
-                  shared_jump_layout(8, 12).pbs == DD_W_F32_D8_K12_PBS &&
-                  shared_jump_layout(8, 12).rbs == DD_W_F32_D8_K12_RBS &&
-                  shared_jump_layout(8, 12).wmax == DD_W_F32_D8_K12_WMAX,
-              "shared-window layout differs from the generated blocks");
+#define DD_CHECK_SHARED(NAME, DW, K)                                                   \
+  static_assert(shared_jump_layout(DW, K).np == DD_##NAME##_NP &&                      \
+                    shared_jump_layout(DW, K).pbs == DD_##NAME##_PBS &&                \
+                    shared_jump_layout(DW, K).rbs == DD_##NAME##_RBS &&                \
+                    shared_jump_layout(DW, K).wmax == DD_##NAME##_WMAX,                \
+                "shared-window layout differs from the generated blocks");
+DD_CHECK_SHARED(W_F32_D8_K12, 8, 12)
+DD_CHECK_SHARED(W_F32_D6_K12, 6, 12)
+DD_CHECK_SHARED(W_F32_D4_K12, 4, 12)
+#undef DD_CHECK_SHARED
 
 // ------------------------------------------------------------------ kernels
 
@@ -1007,10 +1013,19 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
     if (d == 4 && k == 20)
       return *out = make_impl<BodyWin<4, 20, 56, 3, dd_t_f32_d4_k20_w56_channel, false, true>,
                               float>(), true;
+    if (d == 4 && k == 12)
+      return *out = make_impl<BodyWin<4, 12, 48, 4, dd_t_f32_d4_k12_w48_channel, false, true>,
+                              float>(), true;
   }
   if (in_t == DD_F32 && v == 7) {
     if (d == 8 && k == 12)
       return *out = make_impl<BodyWin<8, 12, 48, 3, dd_w_f32_d8_k12_channel, false, true, 62>,
+                              float>(), true;
+    if (d == 6 && k == 12)
+      return *out = make_impl<BodyWin<6, 12, 48, 4, dd_w_f32_d6_k12_channel, false, true, 62>,
+                              float>(), true;
+    if (d == 4 && k == 12)
+      return *out = make_impl<BodyWin<4, 12, 48, 5, dd_w_f32_d4_k12_channel, false, true, 62>,
                               float>(), true;
   }
   if (in_t == DD_F32 && v == 2) {

@@ -58,8 +58,8 @@ TileShape make(int v, int dw, int k, int cc) {
 
 std::vector<TileShape> candidates(dd_dtype in_t) {
   if (in_t == DD_F32)
-    return {make(5, 8, 12, 8), make(5, 8, 20, 6), make(5, 6, 12, 8), make(5, 4, 12, 8),
-            make(1, 8, 12, 8), make(1, 8, 20, 6), make(2, 8, 12, 8), make(0, 8, 8, 8)};
+    return {make(7, 6, 12, 4), make(7, 8, 12, 8), make(6, 8, 12, 8), make(5, 8, 12, 8),
+            make(7, 4, 12, 4), make(5, 8, 20, 6), make(1, 8, 12, 8), make(0, 8, 8, 8)};
   if (in_t == DD_U8)
     return {make(3, 8, 16, 8), make(3, 8, 8, 8), make(3, 8, 16, 4), make(3, 4, 16, 8),
             make(4, 8, 20, 8), make(4, 8, 28, 8), make(4, 4, 28, 8), make(0, 8, 8, 8)};
@@ -68,7 +68,7 @@ std::vector<TileShape> candidates(dd_dtype in_t) {
 }
 
 TileShape builtin_default(dd_dtype in_t) {
-  if (in_t == DD_F32) return make(5, 8, 12, 8);  // register window, host-scheduled reloads
+  if (in_t == DD_F32) return make(7, 6, 12, 4);  // shared windows, threaded jumps, 4 waves/SIMD
   if (in_t == DD_U8) return make(3, 8, 16, 8);   // aligned copies, 16 samples per lane
   return make(3, 8, 8, 8);                        // aligned-copies kernel
 }

@@ -329,6 +329,7 @@ THREAD_CONFIGS = [
     ("t_f32_d8_k12_w48", 8, 12, 48, 3),
     ("t_f32_d8_k20_w56", 8, 20, 56, 2),
     ("t_f32_d4_k20_w56", 4, 20, 56, 3),
+    ("t_f32_d4_k12_w48", 4, 12, 48, 4),
 ]
 
 # fixed SGPRs of the threaded blocks: the block table's address and the jump target
@@ -451,6 +452,8 @@ def gen_thread(name, dw, k, wmax, occ):
 SHARED_CONFIGS = [
     # shared-window flavour: name, DMs per wave, samples per lane, waves per SIMD
     ("w_f32_d8_k12", 8, 12, 3),
+    ("w_f32_d6_k12", 6, 12, 4),
+    ("w_f32_d4_k12", 4, 12, 5),
 ]
 
 
@@ -486,14 +489,16 @@ def gen_shared(name, dw, k, occ):
     and 63 only supply data (their own sums are never stored), so a wave
     owns 62*K output samples.  Block selection and table as gen_thread; the
     table builder and checker are shared with it (window 4K, slack 3K)."""
-    assert k % 4 == 0 and dw in (4, 8)
+    assert k % 4 == 0 and 2 <= dw <= 8
     wmax = 4 * k
     # window registers at the top of the budget: A (2K) then B (K)
     wb = vgpr_budget(occ) - 3 * k
     va, vb = wb, wb + 2 * k
     np_, pbs, rbs = shared_layout(dw, k)
-    nload = "s_load_dwordx8" if dw == 4 else "s_load_dwordx16"
-    vec = "int8v" if dw == 4 else "int16v"
+    # the next channel's 2*DW entries with one scalar load (a wave's entries
+    # are followed by at least 16 words of table)
+    nload = "s_load_dwordx8" if 2 * dw <= 8 else "s_load_dwordx16"
+    vec = "int8v" if 2 * dw <= 8 else "int16v"
     out = []
     out.append(f"// {name}: DW={dw} K={k} OCC={occ}, run A v{va}..v{va + 2 * k - 1}, "
                f"run B v{vb}..v{vb + k - 1}, {dw * np_} plain blocks of {pbs} B, "

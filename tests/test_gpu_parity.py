@@ -232,7 +232,10 @@ TILES_F32 = [
     dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
     dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=6),
     dict(variant=6, dms_per_wave=4, waves=4, tsamp_per_lane=20, chans_per_stage=4),
+    dict(variant=6, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
     dict(variant=7, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=7, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=4),
+    dict(variant=7, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
 ]
 TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}".format(**t) for t in TILES_F32]
 
@@ -271,7 +274,8 @@ def test_threaded_jump_equals_indexed_window(order):
     xt = torch.from_numpy(x).cuda()
     ref = plan.execute_tiled(xt, dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12,
                                       chans_per_stage=8))
-    for v, k, dw in [(6, 12, 8), (6, 20, 8), (6, 20, 4), (7, 12, 8)]:
+    for v, k, dw in [(6, 12, 8), (6, 20, 8), (6, 20, 4), (6, 12, 4), (7, 12, 8), (7, 12, 6),
+                      (7, 12, 4)]:
         y = plan.execute_tiled(xt, dict(variant=v, dms_per_wave=dw, waves=4, tsamp_per_lane=k,
                                         chans_per_stage=8))
         torch.cuda.synchronize()
@@ -412,7 +416,8 @@ def test_autotune_then_execute(dtype):
 def test_one_plan_from_many_threads_and_streams():
     """A fresh plan used by four host threads at once, each on its own stream
     and with its own tile shape: the lazily built device tables are created
-    once under the plan's lock and every result matches the oracle."""
+    once per layout under the plan's lock and every result matches the
+    oracle."""
     import threading
     g = np.random.default_rng(77)
     nchans, ndms, nsamp = 64, 70, 5000
@@ -420,10 +425,12 @@ def test_one_plan_from_many_threads_and_streams():
     plan = dd.Plan.from_delays(tab)
     x = make_input(g, "f32", nchans, nsamp)
     xt = torch.from_numpy(x).cuda()
-    tiles = [dict(variant=5, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
-             dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
-             dict(variant=5, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
-             dict(variant=0, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)]
+    # variants 6 and 7 at 8 DMs per wave share the window shape but not the
+    # block layout, so their jump tables must stay apart
+    tiles = [dict(variant=7, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=4),
+             dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+             dict(variant=7, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
+             dict(variant=5, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8)]
     outs, errs = [None] * 4, []
     barrier = threading.Barrier(4)
 
