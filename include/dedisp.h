@@ -480,6 +480,39 @@ dd_status dd_jump_table_check(const int32_t* entries, const int32_t* rel, int64_
 
 /* ------------------------------------------------------------------------ */
 
+/*
+ * The FP32 pair-sum kernel (tile variant 8) takes channels in groups of g
+ * (pairs) and, per DM tile, builds one LDS row per group and delay pattern
+ * (the shifts of the group's later channels relative to its first); each DM
+ * then adds one run of its pattern's row.  Its table holds, per (tile,
+ * group), the patterns (`aux`: count, then g-1 relative shifts per pattern)
+ * and, per (tile, group, wavefront), a chain of block offsets through the
+ * jump table of the step (`ent`: first block, one next-block offset per DM
+ * slot, one window start per slot).  A wrong offset would be a jump into
+ * arbitrary code, so the library checks every table before upload; these
+ * pure host functions expose the sizes, the builder and the checker so that
+ * tests can plant wrong entries.  No GPU is used.
+ *
+ * dd_pair_table_sizes: words of `ent` and `aux` for tile height td (a
+ * multiple of 4, at most 28), group size g (1..8) and pmax pattern rows per
+ * group.
+ * dd_pair_table_build: fills them for k samples per lane (a multiple of 4),
+ * slot floats per staged row (a multiple of 64) and gps groups per stage;
+ * DD_ERR_NOT_IMPLEMENTED when some (tile, group) has more than pmax
+ * patterns (the library then runs the single-channel kernel).
+ * dd_pair_table_check: DD_OK when every chain visits each DM slot once,
+ * starts with a first-visit window load, ends at the exit, keeps every
+ * window inside the workgroup's LDS, and gives every DM exactly its own
+ * pattern row at its own shift; DD_ERR_STATE otherwise (dd_last_error says
+ * which rule failed).
+ */
+dd_status dd_pair_table_sizes(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax,
+                              int64_t* ent_words, int64_t* aux_words);
+dd_status dd_pair_table_build(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax, int32_t k,
+                              int32_t slot, int32_t gps, int32_t* ent, int32_t* aux);
+dd_status dd_pair_table_check(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax, int32_t k,
+                              int32_t slot, int32_t gps, const int32_t* ent, const int32_t* aux);
+
 const char* dd_status_str(dd_status s);
 const char* dd_last_error(void);
 /* Library version, "major.minor.patch". */

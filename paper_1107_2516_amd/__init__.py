@@ -122,6 +122,9 @@ _SIGS = {
     "dd_subband_plan_destroy": [_P],
     "dd_jump_table_build": [_P, _I64, _I32, _I32, _I32, _P],
     "dd_jump_table_check": [_P, _P, _I64, _I32, _I32, _I32],
+    "dd_pair_table_sizes": [_P, _I32, _I32, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
+    "dd_pair_table_build": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P],
+    "dd_pair_table_check": [_P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P],
 }
 
 

@@ -3,6 +3,8 @@
 #include <cstring>
 #include <new>
 
+#include <algorithm>
+
 #include "dd_internal.h"
 
 namespace dd {
@@ -189,6 +191,62 @@ dd_status dd_jump_table_check(const int32_t* entries, const int32_t* rel, int64_
   if (!rel || !entries || ngroups < 0) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
   if (!jump_shape_ok(dw, k, wmax)) return dd::set_error(DD_ERR_INVALID_ARG, "bad block-table shape");
   return dd::check_jump_entries(entries, rel, ngroups, dd::jump_layout(dw, k, wmax));
+  DD_GUARD_END
+}
+
+}  // extern "C"
+
+namespace {
+bool pair_args_ok(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax, int32_t k,
+                  int32_t slot, int32_t gps) {
+  return plan && td >= 4 && td % 4 == 0 && td / 4 <= 7 && g >= 1 && g <= 8 && pmax >= 1 &&
+         pmax <= 16 && k >= 4 && k % 4 == 0 && k <= 64 && slot > 0 && slot % 64 == 0 && gps >= 1;
+}
+size_t pair_ent_words(const dd_plan* plan, int32_t td, int32_t g) {
+  const size_t ntiles = (plan->ndms + td - 1) / td, ngroups = (plan->nchans + g - 1) / g;
+  return ntiles * ngroups * 4 * dd::kPairEntryWords + 16;
+}
+size_t pair_aux_len(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax) {
+  const size_t ntiles = (plan->ndms + td - 1) / td, ngroups = (plan->nchans + g - 1) / g;
+  return ntiles * ngroups * dd::pair_aux_words(g, pmax) + 4;
+}
+}  // namespace
+
+extern "C" {
+
+dd_status dd_pair_table_sizes(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax,
+                              int64_t* ent_words, int64_t* aux_words) {
+  DD_GUARD_BEGIN
+  if (!plan || !ent_words || !aux_words || td < 4 || td % 4 || g < 1 || g > 8 || pmax < 1)
+    return dd::set_error(DD_ERR_INVALID_ARG, "bad pair-table arguments");
+  *ent_words = static_cast<int64_t>(pair_ent_words(plan, td, g));
+  *aux_words = static_cast<int64_t>(pair_aux_len(plan, td, g, pmax));
+  return DD_OK;
+  DD_GUARD_END
+}
+
+dd_status dd_pair_table_build(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax, int32_t k,
+                              int32_t slot, int32_t gps, int32_t* ent, int32_t* aux) {
+  DD_GUARD_BEGIN
+  if (!ent || !aux || !pair_args_ok(plan, td, g, pmax, k, slot, gps))
+    return dd::set_error(DD_ERR_INVALID_ARG, "bad pair-table arguments");
+  std::vector<int32_t> e, a;
+  const dd::PairShape s{td, g, pmax, slot, gps, 2};
+  dd_status st = dd::build_pair_tables(plan, s, dd::linked_layout(td / 4, k), &e, &a);
+  if (st != DD_OK) return st;
+  std::copy(e.begin(), e.end(), ent);
+  std::copy(a.begin(), a.end(), aux);
+  return DD_OK;
+  DD_GUARD_END
+}
+
+dd_status dd_pair_table_check(const dd_plan* plan, int32_t td, int32_t g, int32_t pmax, int32_t k,
+                              int32_t slot, int32_t gps, const int32_t* ent, const int32_t* aux) {
+  DD_GUARD_BEGIN
+  if (!ent || !aux || !pair_args_ok(plan, td, g, pmax, k, slot, gps))
+    return dd::set_error(DD_ERR_INVALID_ARG, "bad pair-table arguments");
+  const dd::PairShape s{td, g, pmax, slot, gps, 2};
+  return dd::check_pair_tables(plan, s, dd::linked_layout(td / 4, k), ent, aux);
   DD_GUARD_END
 }
 

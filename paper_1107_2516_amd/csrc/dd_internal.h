@@ -73,6 +73,9 @@ struct DeviceTables {
   // window, plain and reload block sizes): the entries are byte offsets into
   // one step's block table, so two layouts never share them
   std::map<std::tuple<int, int, int, int, int, int>, int32_t*> jumptab;
+  // pair-sum entries and pattern records, keyed by the whole pair shape and
+  // block layout (td, G, PMAX, slot, groups per stage, dw, k, np, pbs, rbs, end)
+  std::map<std::vector<int>, std::pair<int32_t*, int32_t*>> pairtab;
 };
 
 }  // namespace dd
@@ -153,6 +156,58 @@ dd_status check_jump_entries(const int32_t* ent, const int32_t* rel, int64_t ngr
 // (tile, channel, wavefront) of the plan for tile height td, checked before
 // upload: [tile][channel][td/dw wavefronts][2*dw].
 dd_status plan_jumptab(dd_plan* plan, int td, const JumpLayout& L, const int32_t** out);
+
+// Pair-sum register window (FP32 variant 8).  Channels are taken in groups
+// of G (pairs); within a DM tile the DMs of a group fall into a few delay
+// patterns (the shifts of channels c+1.. relative to channel c).  Each stage
+// of `gps` groups stages the raw rows of its channels in LDS (row stride
+// slot + 64 floats, the row's first sample at float 4; `nraw` buffers of
+// them, used in turn by consecutive stages), builds one LDS row
+// per (group, pattern) holding the exact sum of the group's channels at the
+// pattern's relative shifts (row (gl*PMAX + p) of the pattern area, which
+// follows the raw area), and then every DM of the tile adds one run of its
+// pattern's row instead of G channel runs.  The DMs of a wavefront are
+// visited in an order chosen per step (group), with linked threaded jumps.
+struct LinkedLayout {
+  int dw, k, np, pbs, rbs, end;
+};
+constexpr LinkedLayout linked_layout(int dw, int k) {
+  return LinkedLayout{dw, k, 3 * k + 1, 8 * k + 12, 8 + 4 * k + 4 + 8 + 8 * k + 4 + 4 * k + 12,
+                      dw * (3 * k + 1) * (8 * k + 12) +
+                          dw * 8 * (8 + 4 * k + 4 + 8 + 8 * k + 4 + 4 * k + 12)};
+}
+struct PairShape {
+  int td, g, pmax, slot, gps;
+  int nraw;  // raw-row buffers (the DMA of later stages lands while earlier ones are summed)
+};
+constexpr int kPairEntryWords = 16;  // per (tile, group, wavefront): start, dw next, dw starts
+constexpr int pair_aux_words(int g, int pmax) { return (1 + pmax * (g - 1) + 3) & ~3; }
+constexpr int pair_raw_stride(int slot) { return slot + 64; }
+constexpr int64_t pair_raw_floats(const PairShape& s) {
+  return static_cast<int64_t>(s.nraw) * s.gps * s.g * pair_raw_stride(s.slot);
+}
+constexpr int64_t pair_lds_floats(const PairShape& s) {
+  return pair_raw_floats(s) + static_cast<int64_t>(s.gps) * s.pmax * s.slot;
+}
+// Host tables for every (tile, group): `aux` [tile][group][pair_aux_words]
+// = npat, then the relative shifts of channels 1..G-1 for each pattern;
+// `ent` [tile][group][td/dw][kPairEntryWords].  DD_ERR_NOT_IMPLEMENTED when
+// some (tile, group) has more than PMAX patterns (the caller then uses the
+// single-channel kernel).
+dd_status build_pair_tables(const dd_plan* plan, const PairShape& s, const LinkedLayout& L,
+                            std::vector<int32_t>* ent, std::vector<int32_t>* aux);
+// Check the tables against the plan by running the schedule they encode:
+// every chain visits each DM slot once and ends at the exit, starts with a
+// first-visit reload block, every window lies inside the workgroup's LDS,
+// every DM's pattern is one of its group's records, and every DM reads its
+// pattern row at exactly its own shift.  DD_ERR_STATE names the first
+// failure.
+dd_status check_pair_tables(const dd_plan* plan, const PairShape& s, const LinkedLayout& L,
+                            const int32_t* ent, const int32_t* aux);
+// Device copies (built, checked and uploaded once per device, shape and
+// layout).
+dd_status plan_pairtab(dd_plan* plan, const PairShape& s, const LinkedLayout& L,
+                       const int32_t** ent, const int32_t** aux);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {

@@ -43,6 +43,8 @@
 //  7  BodyWin:     variant 6 with windows shared between neighbouring lanes:
 //                  a lane reads half its window from LDS and takes the rest
 //                  from the next two lanes through DPP wavefront shifts.
+//  8  BodyPairs:   variant 7 over exact sums of channel pairs: the DMs of a
+//                  tile that share a pair's delay pattern share its sum.
 #include <cstring>
 #include <type_traits>
 
@@ -64,6 +66,7 @@ struct KParams {
   const int32_t* tab;   // [tile][nchans][TD]: rel (variants 0-2), copy offsets (3),
                         // aligned rel (4) or scheduled window entries (5)
   const int32_t* rows;  // [tile][TD]
+  const int32_t* aux;   // variant 8: pattern records [tile][group][aux words]
   int32_t nchans, slot, cc;
   int32_t n_dtiles, n_ttiles, nblocks, per_xcd;
 };
@@ -306,6 +309,215 @@ struct BodyWin {
                                                         : jump_layout(DW, K, WMAX);
   static_assert(LANES == 64 || (JUMP && WMAX == 4 * K && LANES == 62),
                 "shared windows: threaded-jump step, window 4K, two supplying lanes");
+};
+
+// ---------------------------------------------------------------- variant 8
+//
+// Pair sums (exact sub-sum sharing) under the shared-window step.  Channels
+// are taken in groups of G.  Within a DM tile the DMs of a group fall into a
+// few delay patterns (the shifts of channels c+1.. relative to channel c);
+// DMs of one pattern read the group's channels at the same relative shifts,
+// so their G-channel partial sums are one series, shifted.  Each stage of
+// `gps` groups (p.cc) stages its channels' raw rows in LDS by DMA, builds one
+// LDS row per (group, pattern) holding the exact sum of the group's channels
+// at that pattern's shifts (G-1 FP32 adds per sample, in channel order), and
+// then each DM adds one run of its pattern's row per group instead of G runs.
+// Raw rows have a stride of slot + 64 floats and start 4 samples before the
+// window (buffer loads return 0 before sample 0 and past the row end), so
+// the unaligned reads of the build stay inside each raw row.  The DMs of a
+// wavefront are visited in the order the host chose for the group (pattern
+// rows one after the other), through linked threaded jumps; the host checks
+// every table entry before upload (check_pair_tables).
+// One pattern row of a channel pair: dst[t] = a[t] + b[t + dq + M] for every
+// quad t of the slot, two quads per lane and pass with all four reads issued
+// before the adds.  The shifted read's aligned base is clamped into the
+// padded raw row; only quads that no DM reads are ever clamped.
+typedef float pf4 __attribute__((ext_vector_type(4)));
+template <int M>
+__device__ __forceinline__ pf4 pick(const pf4& w0, const pf4& w1) {
+  if constexpr (M == 0) return w0;
+  if constexpr (M == 1) return pf4{w0.y, w0.z, w0.w, w1.x};
+  if constexpr (M == 2) return pf4{w0.z, w0.w, w1.x, w1.y};
+  return pf4{w0.w, w1.x, w1.y, w1.z};
+}
+template <int M>
+__device__ __forceinline__ void build_pair_row(const float* a, const float* b, float* dst, int dq,
+                                               int slot, unsigned ln) {
+  const int nq = slot / 4;
+  for (int q = static_cast<int>(ln); q < nq; q += 128) {
+    const int q1 = q + 64;
+    const int t0 = 4 * q, t1 = 4 * min(q1, nq - 1);
+    const int b0 = min(max(t0 + dq, -4), slot + 52), b1 = min(max(t1 + dq, -4), slot + 52);
+    const pf4 x0 = *reinterpret_cast<const pf4*>(a + t0);
+    const pf4 x1 = *reinterpret_cast<const pf4*>(a + t1);
+    const pf4 u0 = *reinterpret_cast<const pf4*>(b + b0);
+    const pf4 u1 = *reinterpret_cast<const pf4*>(b + b0 + 4);
+    const pf4 v0 = *reinterpret_cast<const pf4*>(b + b1);
+    const pf4 v1 = *reinterpret_cast<const pf4*>(b + b1 + 4);
+    *reinterpret_cast<pf4*>(dst + t0) = x0 + pick<M>(u0, u1);
+    if (q1 < nq) *reinterpret_cast<pf4*>(dst + t1) = x1 + pick<M>(v0, v1);
+  }
+}
+
+template <int DW, int K, int OCC_, int G, int PMAX, int NRAW,
+          void (*STEP)(float*, const int*, unsigned, const int32_t*, int*)>
+struct BodyPairs {
+  static constexpr int TD = 4 * DW, LANES = 62, TT = LANES * K, OCC = OCC_, WMAX = 4 * K;
+  static constexpr int AW = pair_aux_words(G, PMAX);
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* lds = reinterpret_cast<float*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_id();
+    const float* in = static_cast<const float*>(p.in);
+    const int slot = p.slot, gps = p.cc, rs = pair_raw_stride(p.slot);
+    const int ngroups = (p.nchans + G - 1) / G;
+    const int nstage = (ngroups + gps - 1) / gps;
+    float* pr = lds + NRAW * gps * G * rs;
+    const unsigned row_bytes = static_cast<unsigned>(p.nsamp) * 4u;
+    const unsigned lane_addr = static_cast<unsigned>(reinterpret_cast<uintptr_t>(lds)) +
+                               static_cast<unsigned>(lane * K * 4);
+    auto raw_of = [&](int s) { return lds + (s % NRAW) * gps * G * rs; };
+    auto issue = [&](int s) {
+      float* raw = raw_of(s);
+      const int c0 = s * gps * G;
+      const int ncc = min(gps * G, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        // four samples before the window: a negative offset reads as zero
+        const int g0 =
+            static_cast<int>(t0) + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c) - 4;
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(in + static_cast<int64_t>(c) * p.in_stride), 0,
+            static_cast<int>(row_bytes), 0x00020000);
+        float* dst = raw + i * rs;
+        for (int e = 0; e < rs; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rsrc, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(g0 + e + lane) * 4u, 0, 0, 0);
+      }
+    };
+    // pattern rows of stage s: wave w builds rows w, w+4, ... of the stage's
+    // gps*PMAX row slots (a row's shifts are wave-uniform)
+    auto build = [&](int s) {
+      const float* raw = raw_of(s);
+      const int ng = min(gps, ngroups - s * gps);
+      for (int r = wave; r < ng * PMAX; r += 4) {
+        const int gl = r / PMAX, pi = r % PMAX;
+        const int g = s * gps + gl;
+        const int32_t* a = p.aux + (static_cast<int64_t>(dtile) * ngroups + g) * AW;
+        if (pi >= cload1(a)) continue;
+        const int gs = min(G, p.nchans - g * G);
+        const float* src0 = raw + gl * G * rs + 4;
+        float* dst = pr + r * slot;
+        int d[G > 1 ? G - 1 : 1];
+#pragma unroll
+        for (int i = 1; i < G; i++) d[i - 1] = cload1(a + 1 + pi * (G - 1) + (i - 1));
+        // the lane index recomputed here (volatile, so not hoisted): nothing
+        // lane-dependent of the build stays live across the DM phase, whose
+        // accumulators and windows fill the register budget
+        unsigned ln;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n v_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+        if constexpr (G == 2) {
+          if (gs == 2) {
+            // one shifted term: the sub-dword shift is wave-uniform, so each
+            // of the four cases is its own loop with fixed register picks
+            const float* src1 = raw + (gl * G + 1) * rs + 4;
+            const int dq = d[0] & ~3;
+            switch (d[0] & 3) {
+              case 0: build_pair_row<0>(src0, src1, dst, dq, slot, ln); break;
+              case 1: build_pair_row<1>(src0, src1, dst, dq, slot, ln); break;
+              case 2: build_pair_row<2>(src0, src1, dst, dq, slot, ln); break;
+              default: build_pair_row<3>(src0, src1, dst, dq, slot, ln); break;
+            }
+            continue;
+          }
+        }
+        for (int q = static_cast<int>(ln); q < slot / 4; q += 64) {
+          const int t = 4 * q;
+          f4 v = *reinterpret_cast<const f4*>(src0 + t);
+#pragma unroll
+          for (int i = 1; i < G; i++) {
+            if (i >= gs) break;
+            const float* src = raw + (gl * G + i) * rs + 4;
+            // aligned base of the shifted run, kept inside the padded raw row
+            // (only quads no DM reads are ever clamped)
+            const int ab = min(max(t + (d[i - 1] & ~3), -4), slot + 52);
+            const f4 w0 = *reinterpret_cast<const f4*>(src + ab);
+            const f4 w1 = *reinterpret_cast<const f4*>(src + ab + 4);
+            switch (d[i - 1] & 3) {
+              case 0: v += w0; break;
+              case 1: v += f4{w0.y, w0.z, w0.w, w1.x}; break;
+              case 2: v += f4{w0.z, w0.w, w1.x, w1.y}; break;
+              default: v += f4{w0.w, w1.x, w1.y, w1.z}; break;
+            }
+          }
+          *reinterpret_cast<f4*>(dst + t) = v;
+        }
+      }
+    };
+    float acc[DW * K];
+#pragma unroll
+    for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
+    const int32_t* tabw = p.tab + (static_cast<int64_t>(dtile) * ngroups * 4 + wave) * kPairEntryWords;
+    int e[kPairEntryWords];
+    cload_dw<kPairEntryWords>(tabw, e);
+    // with two raw buffers the rows of stage s+1 are requested before stage
+    // s is built, so their DMA overlaps a whole build and DM phase
+    static_assert(NRAW == 1 || NRAW == 2, "one or two raw buffers");
+    issue(0);
+    for (int s = 0; s < nstage; s++) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // raw rows of stage s landed; every wave is done with stage s-1
+      if (NRAW == 2 && s + 1 < nstage) issue(s + 1);
+      build(s);
+      __syncthreads();  // pattern rows of stage s are ready
+      if (NRAW == 1 && s + 1 < nstage) issue(s + 1);
+      const int g0 = s * gps;
+      const int ng = min(gps, ngroups - g0);
+#pragma unroll 1
+      for (int gl = 0; gl < ng; gl++) {
+        int en[kPairEntryWords];
+        const int gn = min(g0 + gl + 1, ngroups - 1);
+        STEP(acc, e, lane_addr, uniform_ptr(tabw + static_cast<int64_t>(gn) * 4 * kPairEntryWords),
+             en);
+#pragma unroll
+        for (int j = 0; j < kPairEntryWords; j++) e[j] = en[j];
+      }
+    }
+    float* out = static_cast<float*>(p.out);
+#pragma unroll
+    for (int j = 0; j < DW; j++) {
+      const int row = p.rows[dtile * TD + wave * DW + j];
+      if (row < 0) continue;
+      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int64_t t = t0 + lane * K + k;
+        if (lane < LANES && t < p.nout) o[t] = acc[j * K + k];
+      }
+    }
+  }
+  // slot: the staged window of a channel (the shared-window kernel's); cc:
+  // groups per stage that fit the LDS share of one workgroup
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    const int s = (TT + span_max + WMAX + 63) & ~63;
+    const size_t budget = 160 * 1024 / OCC;
+    auto total = [&](int c) {
+      return static_cast<size_t>(pair_lds_floats(PairShape{TD, G, PMAX, s, c, NRAW})) * 4;
+    };
+    if (total(1) > budget) return -1;
+    int c = max(1, cc_req);
+    while (c > 1 && total(c) > budget) c--;
+    *slot = s;
+    *cc = c;
+    *lds = total(c);
+    return 0;
+  }
+  static constexpr int table_epd = 0;
+  static constexpr int pair_g = G, pair_pmax = PMAX, pair_nraw = NRAW;
+  static constexpr LinkedLayout table_pair = linked_layout(DW, K);
 };
 
 // ---------------------------------------------------------------- variant 3
@@ -844,6 +1056,11 @@ DD_CHECK_SHARED(W_F32_D8_K12, 8, 12)
 DD_CHECK_SHARED(W_F32_D6_K12, 6, 12)
 DD_CHECK_SHARED(W_F32_D4_K12, 4, 12)
 #undef DD_CHECK_SHARED
+static_assert(linked_layout(6, 12).np == DD_L_F32_D6_K12_NP &&
+                  linked_layout(6, 12).pbs == DD_L_F32_D6_K12_PBS &&
+                  linked_layout(6, 12).rbs == DD_L_F32_D6_K12_RBS &&
+                  linked_layout(6, 12).end == DD_L_F32_D6_K12_END,
+              "linked layout differs from the generated blocks");
 
 // ------------------------------------------------------------------ kernels
 
@@ -923,6 +1140,8 @@ struct Impl {
   const void* batch;
   int td, tt, table_epd, table_ralign, table_win;
   JumpLayout table_jump;  // dw == 0: not a threaded-jump body
+  int pair_g, pair_pmax, pair_nraw;  // pair_g == 0: not a pair-sum body
+  LinkedLayout table_pair;
   size_t in_size;
   bool needs_dword_rows;
 };
@@ -954,6 +1173,17 @@ struct JumpOf<Body, std::void_t<decltype(Body::table_jump)>> {
   static constexpr JumpLayout value = Body::table_jump;
 };
 
+template <class Body, class = void>
+struct PairOf {
+  static constexpr int g = 0, pmax = 0, nraw = 0;
+  static constexpr LinkedLayout layout{};
+};
+template <class Body>
+struct PairOf<Body, std::void_t<decltype(Body::table_pair)>> {
+  static constexpr int g = Body::pair_g, pmax = Body::pair_pmax, nraw = Body::pair_nraw;
+  static constexpr LinkedLayout layout = Body::table_pair;
+};
+
 template <class Body, typename Tin>
 Impl make_impl() {
   Impl m;
@@ -966,6 +1196,10 @@ Impl make_impl() {
   m.table_ralign = RalignOf<Body>::value;
   m.table_win = WinOf<Body>::value;
   m.table_jump = JumpOf<Body>::value;
+  m.pair_g = PairOf<Body>::g;
+  m.pair_pmax = PairOf<Body>::pmax;
+  m.pair_nraw = PairOf<Body>::nraw;
+  m.table_pair = PairOf<Body>::layout;
   m.in_size = sizeof(Tin);
   m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0;
   return m;
@@ -1027,6 +1261,10 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
     if (d == 4 && k == 12)
       return *out = make_impl<BodyWin<4, 12, 48, 5, dd_w_f32_d4_k12_channel, false, true, 62>,
                               float>(), true;
+  }
+  if (in_t == DD_F32 && v == 8) {
+    if (d == 6 && k == 12)
+      return *out = make_impl<BodyPairs<6, 12, 4, 2, 3, 2, dd_l_f32_d6_k12_step>, float>(), true;
   }
   if (in_t == DD_F32 && v == 2) {
     if (d == 8 && k == 20)
@@ -1104,7 +1342,19 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
   if (impl.geometry(tt->span_max, s.chans_per_stage, &slot, &cc, &lds) != 0)
     return set_error(DD_ERR_TOO_LARGE, "shift spread inside a DM tile does not fit LDS");
   const int32_t* tab = tt->d_rel;
-  if (impl.table_epd) {
+  const int32_t* aux = nullptr;
+  if (impl.pair_g) {
+    const PairShape ps{impl.td, impl.pair_g, impl.pair_pmax, slot, cc, impl.pair_nraw};
+    st = plan_pairtab(a.plan, ps, impl.table_pair, &tab, &aux);
+    if (st == DD_ERR_NOT_IMPLEMENTED) {
+      // some channel group of some tile has more delay patterns than pattern
+      // rows: the same DM and time tiling without pair sums
+      TileShape s7 = s;
+      s7.variant = 7;
+      return prepare(s7, in_t, a, out);
+    }
+    if (st != DD_OK) return st;
+  } else if (impl.table_epd) {
     st = plan_aoff(a.plan, impl.td, impl.table_epd, slot, &tab);
     if (st != DD_OK) return st;
   } else if (impl.table_ralign) {
@@ -1132,6 +1382,7 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
   p.base = tt->d_base;
   p.tab = tab;
   p.rows = tt->d_rows;
+  p.aux = aux;
   p.nchans = a.nchans;
   p.slot = slot;
   p.cc = cc;

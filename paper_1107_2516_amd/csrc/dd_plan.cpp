@@ -426,6 +426,249 @@ dd_status plan_jumptab(dd_plan* plan, int td, const JumpLayout& L, const int32_t
   return DD_OK;
 }
 
+
+namespace {
+
+// The tile bases plan_tiles uploads: per (tile, channel) the smallest shift
+// of the tile's real DMs; padding slots repeat the tile's first DM.
+struct TileView {
+  const dd_plan* plan;
+  int td, ntiles;
+  std::vector<int32_t> base;  // [tile][channel]
+  TileView(const dd_plan* p, int td_) : plan(p), td(td_) {
+    const int nch = p->nchans;
+    ntiles = (p->ndms + td - 1) / td;
+    base.assign(static_cast<size_t>(ntiles) * nch, 0);
+    for (int tile = 0; tile < ntiles; tile++) {
+      const int first = tile * td;
+      const int count = std::min(td, p->ndms - first);
+      for (int c = 0; c < nch; c++) {
+        int32_t lo = INT32_MAX;
+        for (int j = 0; j < count; j++)
+          lo = std::min(lo, p->delays[static_cast<size_t>(p->order[first + j]) * nch + c]);
+        base[static_cast<size_t>(tile) * nch + c] = lo;
+      }
+    }
+  }
+  int src(int tile, int j) const {
+    const int first = tile * td;
+    const int count = std::min(td, plan->ndms - first);
+    return plan->order[first + (j < count ? j : 0)];
+  }
+  // shift of slot j of the tile at channel c relative to the staged window
+  int32_t rel(int tile, int j, int c) const {
+    return plan->delays[static_cast<size_t>(src(tile, j)) * plan->nchans + c] -
+           base[static_cast<size_t>(tile) * plan->nchans + c];
+  }
+};
+
+bool pair_shape_ok(const dd_plan* plan, const PairShape& s, const LinkedLayout& L) {
+  return plan && s.td > 0 && s.td % 4 == 0 && s.td / 4 == L.dw && L.dw >= 1 && L.dw <= 7 &&
+         1 + 2 * L.dw <= kPairEntryWords && s.g >= 1 && s.g <= 8 && s.pmax >= 1 && s.gps >= 1 &&
+         s.nraw >= 1 && s.nraw <= 4 &&
+         s.slot > 0 && s.slot % 64 == 0 && L.k > 0 && L.k % 4 == 0 && L.np == 3 * L.k + 1;
+}
+
+}  // namespace
+
+dd_status build_pair_tables(const dd_plan* plan, const PairShape& s, const LinkedLayout& L,
+                            std::vector<int32_t>* ent, std::vector<int32_t>* aux) {
+  if (!pair_shape_ok(plan, s, L)) return set_error(DD_ERR_INVALID_ARG, "bad pair-table shape");
+  const TileView tv(plan, s.td);
+  const int nch = plan->nchans, dw = L.dw, G = s.g;
+  const int ngroups = (nch + G - 1) / G;
+  const int aw = pair_aux_words(G, s.pmax);
+  const int64_t raw_floats = pair_raw_floats(s);
+  const int64_t reload0 = static_cast<int64_t>(dw) * L.np * L.pbs;
+  // +16: each step fetches the next step's 16 words with one scalar load
+  ent->assign(static_cast<size_t>(tv.ntiles) * ngroups * 4 * kPairEntryWords + 16, 0);
+  aux->assign(static_cast<size_t>(tv.ntiles) * ngroups * aw + 4, 0);
+  std::vector<std::vector<int32_t>> pats;
+  std::vector<int> pid(s.td);
+  std::vector<int32_t> key(G), r0(s.td);
+  for (int tile = 0; tile < tv.ntiles; tile++) {
+    for (int g = 0; g < ngroups; g++) {
+      const int c = g * G, gs = std::min(G, nch - c), gl = g % s.gps;
+      pats.clear();
+      for (int q = 0; q < s.td; q++) {
+        r0[q] = tv.rel(tile, q, c);
+        key.assign(G - 1, 0);
+        for (int i = 1; i < gs; i++) key[i - 1] = tv.rel(tile, q, c + i) - r0[q];
+        auto it = std::find(pats.begin(), pats.end(), key);
+        if (it == pats.end()) {
+          if (static_cast<int>(pats.size()) == s.pmax)
+            return set_error(DD_ERR_NOT_IMPLEMENTED, "more delay patterns in a channel group "
+                                                     "than pattern rows");
+          pats.push_back(key);
+          it = pats.end() - 1;
+        }
+        pid[q] = static_cast<int>(it - pats.begin());
+      }
+      int32_t* a = aux->data() + (static_cast<size_t>(tile) * ngroups + g) * aw;
+      a[0] = static_cast<int32_t>(pats.size());
+      for (size_t p = 0; p < pats.size(); p++)
+        for (int i = 0; i < G - 1; i++) a[1 + p * (G - 1) + i] = pats[p][i];
+      for (int w = 0; w < 4; w++) {
+        int32_t* e = ent->data() + ((static_cast<size_t>(tile) * ngroups + g) * 4 + w) * kPairEntryWords;
+        int64_t pos[8], blk[8], st[8];
+        int order[8];
+        for (int j = 0; j < dw; j++) {
+          const int q = w * dw + j;
+          pos[j] = raw_floats + (static_cast<int64_t>(gl) * s.pmax + pid[q]) * s.slot + r0[q];
+          order[j] = j;
+          st[j] = 0;
+        }
+        std::stable_sort(order, order + dw, [&](int x, int y) { return pos[x] < pos[y]; });
+        int64_t wstart = -1;
+        for (int v = 0; v < dw; v++) {
+          const int j = order[v];
+          const int64_t o = pos[j] - wstart;
+          if (v == 0 || o < 0 || o > 3 * L.k) {
+            wstart = pos[j] & ~int64_t(3);
+            const int64_t q4 = pos[j] - wstart;
+            blk[j] = reload0 + ((static_cast<int64_t>(j) * 2 + (v == 0 ? 0 : 1)) * 4 + q4) * L.rbs;
+            st[j] = wstart;
+          } else {
+            blk[j] = (static_cast<int64_t>(j) * L.np + o) * L.pbs;
+          }
+        }
+        for (int j = 0; j < dw; j++)
+          if (blk[j] > INT32_MAX || st[j] > INT32_MAX)
+            return set_error(DD_ERR_TOO_LARGE, "pair table entry beyond 32 bits");
+        e[0] = static_cast<int32_t>(blk[order[0]]);
+        for (int v = 0; v < dw; v++)
+          e[1 + order[v]] = v + 1 < dw ? static_cast<int32_t>(blk[order[v + 1]]) : L.end;
+        for (int j = 0; j < dw; j++) e[1 + dw + j] = static_cast<int32_t>(st[j]);
+      }
+    }
+  }
+  return DD_OK;
+}
+
+dd_status check_pair_tables(const dd_plan* plan, const PairShape& s, const LinkedLayout& L,
+                            const int32_t* ent, const int32_t* aux) {
+  if (!pair_shape_ok(plan, s, L)) return set_error(DD_ERR_INVALID_ARG, "bad pair-table shape");
+  const TileView tv(plan, s.td);
+  const int nch = plan->nchans, dw = L.dw, G = s.g, K = L.k;
+  const int ngroups = (nch + G - 1) / G;
+  const int aw = pair_aux_words(G, s.pmax);
+  const int64_t raw_floats = pair_raw_floats(s);
+  const int64_t lds_floats = pair_lds_floats(s);
+  const int64_t reload0 = static_cast<int64_t>(dw) * L.np * L.pbs;
+  const int64_t end = reload0 + static_cast<int64_t>(dw) * 8 * L.rbs;
+  if (end != L.end) return set_error(DD_ERR_STATE, "pair table: exit offset differs from layout");
+  for (int tile = 0; tile < tv.ntiles; tile++) {
+    for (int g = 0; g < ngroups; g++) {
+      const int c = g * G, gs = std::min(G, nch - c), gl = g % s.gps;
+      const int32_t* a = aux + (static_cast<size_t>(tile) * ngroups + g) * aw;
+      const int npat = a[0];
+      if (npat < 1 || npat > s.pmax) return set_error(DD_ERR_STATE, "pair table: pattern count");
+      for (int w = 0; w < 4; w++) {
+        const int32_t* e =
+            ent + ((static_cast<size_t>(tile) * ngroups + g) * 4 + w) * kPairEntryWords;
+        int64_t need[8];
+        for (int j = 0; j < dw; j++) {
+          const int q = w * dw + j;
+          const int32_t r0 = tv.rel(tile, q, c);
+          int p = 0;
+          for (; p < npat; p++) {
+            bool same = true;
+            for (int i = 1; i < G; i++) {
+              const int32_t want = i < gs ? tv.rel(tile, q, c + i) - r0 : 0;
+              same = same && a[1 + p * (G - 1) + (i - 1)] == want;
+            }
+            if (same) break;
+          }
+          if (p == npat) return set_error(DD_ERR_STATE, "pair table: a DM's pattern has no row");
+          need[j] = raw_floats + (static_cast<int64_t>(gl) * s.pmax + p) * s.slot + r0;
+        }
+        bool seen[8] = {false, false, false, false, false, false, false, false};
+        int64_t off = e[0], wstart = -1;
+        for (int v = 0; v < dw; v++) {
+          int j = -1;
+          int64_t shift = 0;
+          if (off >= 0 && off < reload0) {
+            if (off % L.pbs != 0 || wstart < 0)
+              return set_error(DD_ERR_STATE, "pair table: plain block misaligned or no window");
+            j = static_cast<int>(off / L.pbs / L.np);
+            shift = wstart + (off / L.pbs) % L.np;
+          } else if (off >= reload0 && off < end) {
+            const int64_t b = off - reload0;
+            if (b % L.rbs != 0) return set_error(DD_ERR_STATE, "pair table: reload misaligned");
+            const int64_t idx = b / L.rbs;
+            j = static_cast<int>(idx / 8);
+            const int first = static_cast<int>((idx / 4) % 2) == 0;
+            if (first != (v == 0))
+              return set_error(DD_ERR_STATE, "pair table: first-visit reload out of place");
+            const int64_t st = e[1 + dw + j];
+            if (st < 0 || st % 4 != 0 || st + 65 * static_cast<int64_t>(K) > lds_floats)
+              return set_error(DD_ERR_STATE, "pair table: window outside the LDS");
+            wstart = st;
+            shift = st + idx % 4;
+          } else {
+            return set_error(DD_ERR_STATE, "pair table: offset outside the block table");
+          }
+          if (v == 0 && off < reload0)
+            return set_error(DD_ERR_STATE, "pair table: a step must start with a reload");
+          if (seen[j]) return set_error(DD_ERR_STATE, "pair table: a DM visited twice");
+          seen[j] = true;
+          if (shift != need[j]) return set_error(DD_ERR_STATE, "pair table: wrong shift");
+          off = e[1 + j];
+        }
+        if (off != end) return set_error(DD_ERR_STATE, "pair table: chain does not end at the exit");
+      }
+    }
+  }
+  return DD_OK;
+}
+
+dd_status plan_pairtab(dd_plan* plan, const PairShape& s, const LinkedLayout& L,
+                       const int32_t** ent, const int32_t** aux) {
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  const std::vector<int> key = {s.td,   s.g, s.pmax, s.slot,  s.gps, s.nraw,
+                                L.dw,   L.k, L.np,   L.pbs,   L.rbs, L.end};
+  {
+    std::lock_guard<std::mutex> lk(plan->mu);
+    auto& m = plan->dev[dev].pairtab;
+    auto it = m.find(key);
+    if (it != m.end()) {
+      *ent = it->second.first;
+      *aux = it->second.second;
+      return DD_OK;
+    }
+  }
+  std::vector<int32_t> he, ha;
+  dd_status st = build_pair_tables(plan, s, L, &he, &ha);
+  if (st != DD_OK) return st;
+  st = check_pair_tables(plan, s, L, he.data(), ha.data());
+  if (st != DD_OK) return st;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  auto& m = plan->dev[dev].pairtab;
+  auto it = m.find(key);
+  if (it != m.end()) {  // another thread uploaded the same tables meanwhile
+    *ent = it->second.first;
+    *aux = it->second.second;
+    return DD_OK;
+  }
+  int32_t *de = nullptr, *da = nullptr;
+  hipError_t err = hipMalloc(&de, he.size() * sizeof(int32_t));
+  if (err == hipSuccess) err = hipMalloc(&da, ha.size() * sizeof(int32_t));
+  if (err == hipSuccess)
+    err = hipMemcpy(de, he.data(), he.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(da, ha.data(), ha.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(de);
+    (void)hipFree(da);
+    return hip_error(err, "uploading the pair tables");
+  }
+  m.emplace(key, std::make_pair(de, da));
+  *ent = de;
+  *aux = da;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 dd_plan::~dd_plan() {
@@ -442,6 +685,10 @@ dd_plan::~dd_plan() {
     for (auto& t : kv.second.ralign) (void)hipFree(t.second);
     for (auto& t : kv.second.wintab) (void)hipFree(t.second);
     for (auto& t : kv.second.jumptab) (void)hipFree(t.second);
+    for (auto& t : kv.second.pairtab) {
+      (void)hipFree(t.second.first);
+      (void)hipFree(t.second.second);
+    }
     (void)hipSetDevice(cur);
   }
 }

@@ -594,6 +594,135 @@ def gen_shared(name, dw, k, occ):
     return "\n".join(out)
 
 
+LINKED_CONFIGS = [
+    # linked shared-window flavour: name, DMs per wave, samples per lane, waves per SIMD
+    ("l_f32_d6_k12", 6, 12, 4),
+]
+
+
+def linked_layout(dw, k):
+    """Byte layout of the linked block table: DW*NP plain blocks of PBS bytes
+    (as the shared-window flavour), then DW*8 reload blocks of RBS bytes
+    (window sub-offset q in 0..3, times 'first visit of the step' or not),
+    then the exit at END."""
+    np_ = 3 * k + 1
+    pbs = 8 * k + 12
+    rbs = 8 + 8 * (k // 2) + 4 + 8 + 8 * k + 4 + 4 * k + 12
+    end = dw * np_ * pbs + dw * 8 * rbs
+    return np_, pbs, rbs, end
+
+
+def gen_linked(name, dw, k, occ):
+    """Linked flavour of the shared-window step: the DMs of a wavefront are
+    visited in an order chosen by the host for each step (so DMs that read
+    the same LDS row run back to back).  A step's entries are: the offset of
+    the first block, then one 'next' offset per DM slot (the block that runs
+    after that slot's block; the exit for the last one), then one window
+    start per slot (LDS float offset from the workgroup's LDS base, used by
+    reload blocks).  Every block ends with the jump to its slot's 'next'.
+    The first block of a step is always a 'first visit' reload block, which
+    issues the scalar load of the next step's entries once its window has
+    arrived; other reload blocks do not.  Windows are shared between lanes
+    as in gen_shared (lanes 62 and 63 only supply data).  The host builds
+    and checks every entry (plan_linkedtab)."""
+    assert k % 4 == 0 and 2 <= dw <= 7  # 1 + 2*DW entries fit one s_load_dwordx16
+    wmax = 4 * k
+    wb = vgpr_budget(occ) - 3 * k
+    va, vb = wb, wb + 2 * k
+    np_, pbs, rbs, end = linked_layout(dw, k)
+    out = []
+    out.append(f"// {name}: DW={dw} K={k} OCC={occ}, run A v{va}..v{va + 2 * k - 1}, "
+               f"run B v{vb}..v{vb + k - 1}, {dw * np_} plain blocks of {pbs} B, "
+               f"{dw * 8} reload blocks of {rbs} B, exit at {end}")
+    up = name.upper()
+    out.append(f"#define DD_{up}_NP {np_}")
+    out.append(f"#define DD_{up}_PBS {pbs}")
+    out.append(f"#define DD_{up}_RBS {rbs}")
+    out.append(f"#define DD_{up}_END {end}")
+    out.append(f"#define DD_{up}_WMAX {wmax}")
+    out.append(f"__device__ __forceinline__ void dd_{name}_step(float* acc, const int* e, unsigned addr, const int32_t* next, int* en) {{")
+    out += ["  unsigned va;", "  int16v nv;"]
+    out.append("  asm volatile(")
+    out.append(f'      "s_getpc_b64 s[{TPC}:{TPC + 1}]\\n"')
+    out.append('      ".Lpc%=:\\n"')
+    out.append(f'      "s_add_u32 s{TPC}, s{TPC}, .Ltab%=-.Lpc%=\\n"')
+    out.append(f'      "s_addc_u32 s{TPC + 1}, s{TPC + 1}, 0\\n"')
+    out.append(f'      "s_add_u32 s{TTG}, s{TPC}, %[st]\\n"')
+    out.append(f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"')
+    out.append(f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"')
+    out.append('      ".p2align 6\\n"')
+    out.append('      ".Ltab%=:\\n"')
+
+    def tail(j):
+        return [f'      "s_add_u32 s{TTG}, s{TPC}, %[n{j}]\\n"',
+                f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"',
+                f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"']
+
+    def add(j, i, w):
+        if w < 2 * k:
+            return f'      "v_add_f32_e32 %[a{j}_{i}], v{va + w}, %[a{j}_{i}]\\n"', 4
+        if w < 3 * k:
+            return f'      "v_add_f32_e32 %[a{j}_{i}], v{vb + w - 2 * k}, %[a{j}_{i}]\\n"', 4
+        return (f'      "v_add_f32_dpp %[a{j}_{i}], v{vb + w - 3 * k}, %[a{j}_{i}] '
+                f'wave_shl:1 row_mask:0xf bank_mask:0xf\\n"', 8)
+
+    def place(label, off):
+        return [f'      "{label}:\\n"',
+                f'      ".if ({label}-.Ltab%=) != {off}\\n .error \\"block table misplaced\\"\\n .endif\\n"']
+
+    for j in range(dw):
+        for o in range(np_):
+            out += place(f".Lp%=_{j}_{o}", (j * np_ + o) * pbs)
+            size = 0
+            for i in range(k):
+                line, n = add(j, i, o + i)
+                out.append(line)
+                size += n
+            out += tail(j)
+            size += 12
+            out += ['      "s_nop 0\\n"'] * ((pbs - size) // 4)
+    base = dw * np_ * pbs
+    for j in range(dw):
+        for f in range(2):
+            for q in range(4):
+                out += place(f".Lr%=_{j}_{f}_{q}", base + ((j * 2 + f) * 4 + q) * rbs)
+                out.append(f'      "s_lshl_b32 s{TTG}, %[s{j}], 2\\n"')
+                out.append(f'      "v_add_u32_e32 %[va], s{TTG}, %[addr]\\n"')
+                for i in range(k // 2):
+                    off = f" offset:{16 * i}" if i else ""
+                    out.append(f'      "ds_read_b128 v[{va + 4 * i}:{va + 4 * i + 3}], %[va]{off}\\n"')
+                out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+                if f == 0:
+                    out.append('      "s_load_dwordx16 %[rn], %[tp], 0\\n"')
+                else:
+                    out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
+                for m in range(k):
+                    out.append(f'      "v_mov_b32_dpp v{vb + m}, v{va + k + m} wave_shl:1 '
+                               f'row_mask:0xf bank_mask:0xf\\n"')
+                out.append('      "s_nop 1\\n"')
+                for i in range(k):
+                    out.append(add(j, i, q + i)[0])
+                out += tail(j)
+    out += place(".Lend%=", end)
+    out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+    outs = []
+    for j in range(dw):
+        for kk in range(k):
+            outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
+    outs += ['[va] "=&v"(va)', '[rn] "=&s"(nv)']
+    ins = ['[addr] "v"(addr)', '[tp] "s"(next)', '[st] "s"(e[0])']
+    ins += [f'[n{j}] "s"(e[{1 + j}])' for j in range(dw)]
+    ins += [f'[s{j}] "s"(e[{1 + dw + j}])' for j in range(dw)]
+    clob = [f'"v{wb + i}"' for i in range(3 * k)]
+    clob += [f'"s{i}"' for i in (TPC, TPC + 1, TTG, TTG + 1)] + ['"scc"', '"memory"']
+    out.append("      : " + ",\n        ".join(outs))
+    out.append("      : " + ", ".join(ins))
+    out.append("      : " + ", ".join(clob) + ");")
+    out.append("  for (int i = 0; i < 16; i++) en[i] = nv[i];")
+    out.append("}")
+    return "\n".join(out)
+
+
 def main():
     print("// Generated by gen_window_asm.py; do not edit by hand.")
     print("#pragma once")
@@ -617,6 +746,9 @@ def main():
         print()
     for cfg in SHARED_CONFIGS:
         print(gen_shared(*cfg))
+        print()
+    for cfg in LINKED_CONFIGS:
+        print(gen_linked(*cfg))
         print()
 
 
