@@ -76,6 +76,8 @@ struct DeviceTables {
   // pair-sum entries and pattern records, keyed by the whole pair shape and
   // block layout (td, G, PMAX, slot, groups per stage, dw, k, np, pbs, rbs, end)
   std::map<std::vector<int>, std::pair<int32_t*, int32_t*>> pairtab;
+  // 8-bit pair-sum rows and offsets, keyed by (td, idw, slotp, cc, rmax)
+  std::map<std::vector<int>, std::pair<int32_t*, int32_t*>> pairu8;
 };
 
 }  // namespace dd
@@ -208,6 +210,34 @@ dd_status check_pair_tables(const dd_plan* plan, const PairShape& s, const Linke
 // layout).
 dd_status plan_pairtab(dd_plan* plan, const PairShape& s, const LinkedLayout& L,
                        const int32_t** ent, const int32_t** aux);
+
+// 8-bit pair sums (variant 9).  Channels are taken in pairs (c, c+1) and,
+// per DM tile and stage of `cc` channels, the DMs of a pair fall into a few
+// delay patterns (the shift of channel c+1 relative to c).  Each stage
+// stages its raw 8-bit rows (one margin dword before the window), builds one
+// pattern row per (pair, pattern) as 16-bit sums of the two channels, in two
+// copies shifted by one sample (so every DM reads whole dwords of two
+// samples), and each DM adds one dword per two samples per pair.
+// `rows` [tile][stage][1 + 2*rmax]: row count, then per row the pair's index
+// in the stage and the byte shift of its second channel relative to the
+// first (both measured in the staged rows, which start at the dword holding
+// the tile's smallest shift); `offs` (uint16) [tile][pair][td]: the byte
+// offset of a DM's first dword in the stage's pattern-row area,
+// 4 * ((row*2 + (R & 1)) * slotp + (R >> 1)) with R = (base & 3) + rel of
+// the pair's first channel.
+struct PairU8Shape {
+  int td, idw, slotp, cc, rmax;  // idw: dwords per lane (two samples each)
+};
+constexpr int pairu8_raw_dwords(int slotp) { return (slotp / 2 + 2 + 63) & ~63; }
+dd_status build_pairu8_tables(const dd_plan* plan, const PairU8Shape& s,
+                              std::vector<int32_t>* rows, std::vector<uint16_t>* offs);
+// Every DM of every pair reads its own pattern row (the row of its pair with
+// its own relative shift), in the copy of its own parity, at its own dword,
+// and all its reads stay inside the row; at most rmax rows per stage.
+dd_status check_pairu8_tables(const dd_plan* plan, const PairU8Shape& s, const int32_t* rows,
+                              const uint16_t* offs);
+dd_status plan_pairu8(dd_plan* plan, const PairU8Shape& s, const int32_t** rows,
+                      const int32_t** offs);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {

@@ -45,6 +45,8 @@
 //                  from the next two lanes through DPP wavefront shifts.
 //  8  BodyPairs:   variant 7 over exact sums of channel pairs: the DMs of a
 //                  tile that share a pair's delay pattern share its sum.
+//  9  BodyPairsU8: 8-bit input; 16-bit sums of channel pairs per delay
+//                  pattern, one v_add_u32 per two samples per pair and DM.
 #include <cstring>
 #include <type_traits>
 
@@ -66,7 +68,8 @@ struct KParams {
   const int32_t* tab;   // [tile][nchans][TD]: rel (variants 0-2), copy offsets (3),
                         // aligned rel (4) or scheduled window entries (5)
   const int32_t* rows;  // [tile][TD]
-  const int32_t* aux;   // variant 8: pattern records [tile][group][aux words]
+  const int32_t* aux;   // variants 8, 9: pattern records
+  int32_t aux_w;        // variant 9: words per (tile, stage) record
   int32_t nchans, slot, cc;
   int32_t n_dtiles, n_ttiles, nblocks, per_xcd;
 };
@@ -518,6 +521,208 @@ struct BodyPairs {
   static constexpr int table_epd = 0;
   static constexpr int pair_g = G, pair_pmax = PMAX, pair_nraw = NRAW;
   static constexpr LinkedLayout table_pair = linked_layout(DW, K);
+};
+
+// ---------------------------------------------------------------- variant 9
+//
+// 8-bit pair sums.  Channels are taken in pairs (c, c+1); within a DM tile
+// the DMs of a pair fall into a few delay patterns (the shift of c+1
+// relative to c).  A stage of cc channels lands its raw rows in LDS by DMA
+// (one margin dword before each window; bytes past the row end read as 0 and
+// the partial last dword is written in by the wave that staged the row),
+// then builds, for every (pair, pattern) of the stage that the host listed,
+// a pattern row of 16-bit sums S[t] = x_c[t] + x_c+1[t + d] in two copies
+// shifted by one sample: dword w of copy m holds (S[2w+m], S[2w+m+1]).  A DM
+// then reads one dword per two output samples and pair at a dword-aligned
+// host offset (copy R & 1, dword R >> 1) and adds it to 16-bit-lane
+// accumulators with one v_add_u32, emptied into the int32 output every 128
+// pairs (128 * 510 < 2^16).  Lane l owns the dwords l + 64i, i < IDW, so
+// each read is a ds_read2st64_b32 of two dwords.
+template <int DW, int IDW, int OCC_>
+struct BodyPairsU8 {
+  static constexpr int TD = 4 * DW, TT = 128 * IDW, OCC = OCC_;
+  static_assert(IDW % 2 == 0, "dwords per lane come in read2 pairs");
+  __host__ __device__ static constexpr int table_dwords(int cc) {
+    return ((cc + 1) / 2 * TD / 2 + 63) & ~63;
+  }
+  // pattern rows that fit beside cc raw rows and the two offset tables
+  __host__ __device__ static constexpr int rmax_for(int slotp, int cc, int lds_dwords) {
+    return (lds_dwords - cc * pairu8_raw_dwords(slotp) - 2 * table_dwords(cc)) / (2 * slotp);
+  }
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* lds = reinterpret_cast<uint32_t*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_id();
+    const unsigned char* in = static_cast<const unsigned char*>(p.in);
+    const int slotp = p.slot, cc = p.cc, slotr = pairu8_raw_dwords(p.slot);
+    const int nstage = (p.nchans + cc - 1) / cc;
+    const int npairs = (p.nchans + 1) / 2;
+    const int rw = p.aux_w;  // words per stage record: 1 + 2 * pattern rows
+    const int64_t row_bytes = p.in_stride;
+    const int full_dwords = static_cast<int>(p.nsamp / 4);
+    const int tail = static_cast<int>(p.nsamp % 4);
+    const int tabd = table_dwords(cc);
+    uint32_t* raw = lds;
+    uint32_t* tabl = raw + cc * slotr;
+    uint32_t* pr = tabl + 2 * tabd;
+    auto window_dword = [&](int c) -> int {
+      return static_cast<int>((t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> 2);
+    };
+    auto issue = [&](int s, int buf) {
+      const int c0 = s * cc;
+      const int ncc = min(cc, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int gd = window_dword(c) - 1;  // one margin dword; -1 reads as zero
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char*>(in + static_cast<int64_t>(c) * row_bytes), 0,
+            full_dwords * 4, 0x00020000);
+        uint32_t* dst = raw + i * slotr;
+        for (int e = 0; e < slotr; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
+      }
+      if (wave == 3) {  // the stage's DM offsets, [pair][TD] uint16
+        const int np = (ncc + 1) / 2;
+        const uint16_t* tp = reinterpret_cast<const uint16_t*>(p.tab) +
+                             (static_cast<int64_t>(dtile) * npairs + c0 / 2) * TD;
+        __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(tp), 0, np * TD * 2, 0x00020000);
+        uint32_t* dst = tabl + buf * tabd;
+        for (int e = 0; e < np * TD / 2; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rt, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(e + lane) * 4u, 0, 0, 0);
+      }
+    };
+    // the partial last dword of a row (buffer loads read whole dwords only),
+    // written into the staged rows by the wave that staged them
+    auto patch_tails = [&](int s) {
+      if (!tail) return;
+      const int c0 = s * cc;
+      const int ncc = min(cc, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int idx = full_dwords - (window_dword(c) - 1);
+        if (lane == 0 && idx >= 0 && idx < slotr) {
+          const unsigned char* rp = in + static_cast<int64_t>(c) * row_bytes +
+                                    static_cast<int64_t>(full_dwords) * 4;
+          uint32_t v = 0;
+          for (int k = 0; k < tail; k++) v |= static_cast<uint32_t>(rp[k]) << (8 * k);
+          raw[i * slotr + idx] = v;
+        }
+      }
+    };
+    // pattern rows of stage s: wave w builds rows w, w+4, ... (a row's pair
+    // and shift are wave-uniform scalar loads)
+    auto build = [&](int s) {
+      const int32_t* rec = p.aux + (static_cast<int64_t>(dtile) * nstage + s) * rw;
+      const int nrows = cload1(rec);
+      const int units = slotp / 2;
+      const int c0 = s * cc;
+      for (int row = wave; row < nrows; row += 4) {
+        const int pl = cload1(rec + 1 + 2 * row);
+        const int d = cload1(rec + 2 + 2 * row);
+        const bool two = c0 + 2 * pl + 1 < p.nchans;
+        const uint32_t* xr = raw + (2 * pl) * slotr + 1;  // + margin dword
+        const uint32_t* yr = raw + (2 * pl + 1) * slotr;
+        uint32_t* r0 = pr + (2 * row) * slotp;
+        uint32_t* r1 = r0 + slotp;
+        for (int u = lane; u < units; u += 64) {
+          const uint32_t xa = xr[u], xb = xr[u + 1];
+          uint32_t ya = 0, yb = 0;
+          if (two) {
+            // dword of x_c+1 at byte 4u + d, kept inside the row (only units
+            // that no DM reads are ever clamped)
+            const int i0 = min(max(u + (d >> 2) + 1, 0), slotr - 3);
+            const uint32_t y0 = yr[i0], y1 = yr[i0 + 1], y2 = yr[i0 + 2];
+            ya = __builtin_amdgcn_alignbyte(y1, y0, static_cast<unsigned>(d & 3));
+            yb = __builtin_amdgcn_alignbyte(y2, y1, static_cast<unsigned>(d & 3));
+          }
+          auto pick = [&](unsigned sel) {
+            return __builtin_amdgcn_perm(xb, xa, sel) + __builtin_amdgcn_perm(yb, ya, sel);
+          };
+          *reinterpret_cast<uint2*>(r0 + 2 * u) = make_uint2(pick(0x0c010c00u), pick(0x0c030c02u));
+          *reinterpret_cast<uint2*>(r1 + 2 * u) = make_uint2(pick(0x0c020c01u), pick(0x0c040c03u));
+        }
+      }
+    };
+    uint32_t acc[DW][IDW];
+#pragma unroll
+    for (int j = 0; j < DW; j++)
+#pragma unroll
+      for (int i = 0; i < IDW; i++) acc[j][i] = 0u;
+    bool first = true;
+    auto flush = [&]() {
+#pragma unroll
+      for (int j = 0; j < DW; j++) {
+        const int row = p.rows[dtile * TD + wave * DW + j];
+        if (row >= 0) {
+          int32_t* o = static_cast<int32_t*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+          for (int i = 0; i < IDW; i++) {
+            const int64_t tb = t0 + 2 * static_cast<int64_t>(lane + 64 * i);
+            const int32_t v0 = static_cast<int32_t>(acc[j][i] & 0xffffu);
+            const int32_t v1 = static_cast<int32_t>(acc[j][i] >> 16);
+            if (tb < p.nout) o[tb] = first ? v0 : o[tb] + v0;
+            if (tb + 1 < p.nout) o[tb + 1] = first ? v1 : o[tb + 1] + v1;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < IDW; i++) acc[j][i] = 0u;
+      }
+      first = false;
+    };
+    int since_flush = 0;
+    issue(0, 0);
+    for (int s = 0; s < nstage; s++) {
+      const int buf = s & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      patch_tails(s);
+      __syncthreads();  // raw rows of stage s landed; every wave is done with stage s-1's rows
+      build(s);
+      __syncthreads();  // pattern rows of stage s ready; the raw area is free
+      if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+      const int np = (min(cc, p.nchans - s * cc) + 1) / 2;
+      const uint32_t* tb = tabl + buf * tabd + wave * (DW / 2);
+      for (int pl = 0; pl < np; pl++) {
+        uint32_t w[DW / 2];
+#pragma unroll
+        for (int k = 0; k < DW / 2; k++) w[k] = tb[pl * (TD / 2) + k];
+#pragma unroll
+        for (int j = 0; j < DW; j++) {
+          const unsigned off = (w[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+          const uint32_t* src =
+              reinterpret_cast<const uint32_t*>(reinterpret_cast<const unsigned char*>(pr) + off) + lane;
+#pragma unroll
+          for (int i = 0; i < IDW; i++) acc[j][i] += src[64 * i];
+        }
+        if (++since_flush > 127) {
+          flush();
+          since_flush = 0;
+        }
+      }
+    }
+    if (since_flush || first) flush();
+  }
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    // a DM's first dword is (R >> 1) with R <= span_max + 3; it reads 64*IDW dwords
+    const int sp = (64 * IDW + (span_max + 3) / 2 + 1 + 63) & ~63;
+    const int budget = 160 * 1024 / OCC / 4;  // dwords
+    int c = max(2, cc_req & ~1);
+    // at least cc + 2 pattern rows per stage (about two per pair, and room
+    // for a stage whose pairs need a third)
+    while (c > 2 && rmax_for(sp, c, budget) < c + 2) c -= 2;
+    if (rmax_for(sp, c, budget) < c + 2) return -1;
+    *slot = sp;
+    *cc = c;
+    *lds = static_cast<size_t>(budget) * 4;
+    return 0;
+  }
+  static constexpr int table_epd = 0;
+  static constexpr int pairu8_idw = IDW;
 };
 
 // ---------------------------------------------------------------- variant 3
@@ -1141,6 +1346,8 @@ struct Impl {
   int td, tt, table_epd, table_ralign, table_win;
   JumpLayout table_jump;  // dw == 0: not a threaded-jump body
   int pair_g, pair_pmax, pair_nraw;  // pair_g == 0: not a pair-sum body
+  int pairu8_idw;                    // 0: not an 8-bit pair-sum body
+  int (*pairu8_rmax)(int slotp, int cc, int lds_dwords);
   LinkedLayout table_pair;
   size_t in_size;
   bool needs_dword_rows;
@@ -1184,6 +1391,17 @@ struct PairOf<Body, std::void_t<decltype(Body::table_pair)>> {
   static constexpr LinkedLayout layout = Body::table_pair;
 };
 
+template <class Body, class = void>
+struct PairU8Of {
+  static constexpr int idw = 0;
+  static int rmax(int, int, int) { return 0; }
+};
+template <class Body>
+struct PairU8Of<Body, std::void_t<decltype(Body::pairu8_idw)>> {
+  static constexpr int idw = Body::pairu8_idw;
+  static int rmax(int slotp, int cc, int lds_dwords) { return Body::rmax_for(slotp, cc, lds_dwords); }
+};
+
 template <class Body, typename Tin>
 Impl make_impl() {
   Impl m;
@@ -1199,9 +1417,11 @@ Impl make_impl() {
   m.pair_g = PairOf<Body>::g;
   m.pair_pmax = PairOf<Body>::pmax;
   m.pair_nraw = PairOf<Body>::nraw;
+  m.pairu8_idw = PairU8Of<Body>::idw;
+  m.pairu8_rmax = &PairU8Of<Body>::rmax;
   m.table_pair = PairOf<Body>::layout;
   m.in_size = sizeof(Tin);
-  m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0;
+  m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0 || PairU8Of<Body>::idw != 0;
   return m;
 }
 
@@ -1279,6 +1499,9 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
     if (d == 4 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 4, 4, 4>, uint8_t>(), true;
     if (d == 8 && k == 16) return *out = make_impl<BodyCopies<uint8_t, 8, 4, 4>, uint8_t>(), true;
   }
+  if (in_t == DD_U8 && v == 9) {
+    if (d == 8 && k == 16) return *out = make_impl<BodyPairsU8<8, 8, 4>, uint8_t>(), true;
+  }
   if (in_t == DD_U8 && v == 4) {
     if (d == 8 && k == 28)
       return *out = make_impl<BodyWinX<uint8_t, 8, 28, 84, 2, uint32_t, dd_u8p_d8_k28_w84_channel>,
@@ -1343,7 +1566,21 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
     return set_error(DD_ERR_TOO_LARGE, "shift spread inside a DM tile does not fit LDS");
   const int32_t* tab = tt->d_rel;
   const int32_t* aux = nullptr;
-  if (impl.pair_g) {
+  int aux_w = 0;
+  if (impl.pairu8_idw) {
+    const int rmax = impl.pairu8_rmax(slot, cc, static_cast<int>(lds / 4));
+    const PairU8Shape ps{impl.td, impl.pairu8_idw, slot, cc, rmax};
+    st = plan_pairu8(a.plan, ps, &aux, &tab);
+    if (st == DD_ERR_NOT_IMPLEMENTED) {
+      // some stage needs more pattern rows than fit: the aligned-copies kernel
+      TileShape s3 = s;
+      s3.variant = 3;
+      s3.tsamp_per_lane = 16;
+      return prepare(s3, in_t, a, out);
+    }
+    if (st != DD_OK) return st;
+    aux_w = 1 + 2 * rmax;
+  } else if (impl.pair_g) {
     const PairShape ps{impl.td, impl.pair_g, impl.pair_pmax, slot, cc, impl.pair_nraw};
     st = plan_pairtab(a.plan, ps, impl.table_pair, &tab, &aux);
     if (st == DD_ERR_NOT_IMPLEMENTED) {
@@ -1383,6 +1620,7 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
   p.tab = tab;
   p.rows = tt->d_rows;
   p.aux = aux;
+  p.aux_w = aux_w;
   p.nchans = a.nchans;
   p.slot = slot;
   p.cc = cc;

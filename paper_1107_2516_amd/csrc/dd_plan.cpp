@@ -669,6 +669,155 @@ dd_status plan_pairtab(dd_plan* plan, const PairShape& s, const LinkedLayout& L,
   return DD_OK;
 }
 
+
+namespace {
+bool pairu8_shape_ok(const dd_plan* plan, const PairU8Shape& s) {
+  return plan && s.td >= 1 && s.idw >= 2 && s.idw % 2 == 0 && s.slotp > 0 && s.slotp % 64 == 0 &&
+         s.cc >= 2 && s.cc % 2 == 0 && s.rmax >= 1 && s.rmax <= 64;
+}
+}  // namespace
+
+dd_status build_pairu8_tables(const dd_plan* plan, const PairU8Shape& s,
+                              std::vector<int32_t>* rows, std::vector<uint16_t>* offs) {
+  if (!pairu8_shape_ok(plan, s)) return set_error(DD_ERR_INVALID_ARG, "bad 8-bit pair shape");
+  const TileView tv(plan, s.td);
+  const int nch = plan->nchans;
+  const int npairs = (nch + 1) / 2;
+  const int nstage = (nch + s.cc - 1) / s.cc;
+  const int rw = 1 + 2 * s.rmax;
+  rows->assign(static_cast<size_t>(tv.ntiles) * nstage * rw + 4, 0);
+  offs->assign(static_cast<size_t>(tv.ntiles) * npairs * s.td + 16, 0);
+  std::vector<int32_t> R0(s.td), d1(s.td), pat;
+  for (int tile = 0; tile < tv.ntiles; tile++) {
+    for (int st = 0; st < nstage; st++) {
+      int32_t* rec = rows->data() + (static_cast<size_t>(tile) * nstage + st) * rw;
+      int nrows = 0;
+      const int c0 = st * s.cc, ncc = std::min(s.cc, nch - c0);
+      for (int pl = 0; pl < (ncc + 1) / 2; pl++) {
+        const int c = c0 + 2 * pl, g = c / 2;
+        const bool two = c + 1 < nch;
+        const int32_t a0 = tv.base[static_cast<size_t>(tile) * nch + c] & 3;
+        const int32_t a1 = two ? tv.base[static_cast<size_t>(tile) * nch + c + 1] & 3 : 0;
+        pat.clear();
+        for (int q = 0; q < s.td; q++) {
+          R0[q] = a0 + tv.rel(tile, q, c);
+          d1[q] = two ? a1 + tv.rel(tile, q, c + 1) - R0[q] : 0;
+          if (std::find(pat.begin(), pat.end(), d1[q]) == pat.end()) pat.push_back(d1[q]);
+        }
+        if (nrows + static_cast<int>(pat.size()) > s.rmax)
+          return set_error(DD_ERR_NOT_IMPLEMENTED,
+                           "more pattern rows in a stage than the LDS holds");
+        for (int q = 0; q < s.td; q++) {
+          const int row = nrows + static_cast<int>(std::find(pat.begin(), pat.end(), d1[q]) -
+                                                   pat.begin());
+          const int64_t b =
+              4 * ((static_cast<int64_t>(row) * 2 + (R0[q] & 1)) * s.slotp + (R0[q] >> 1));
+          if (b > 0xffff) return set_error(DD_ERR_TOO_LARGE, "pattern row offset beyond 16 bits");
+          (*offs)[(static_cast<size_t>(tile) * npairs + g) * s.td + q] = static_cast<uint16_t>(b);
+        }
+        for (size_t p = 0; p < pat.size(); p++) {
+          rec[1 + 2 * (nrows + p)] = pl;
+          rec[2 + 2 * (nrows + p)] = pat[p];
+        }
+        nrows += static_cast<int>(pat.size());
+      }
+      rec[0] = nrows;
+    }
+  }
+  return DD_OK;
+}
+
+dd_status check_pairu8_tables(const dd_plan* plan, const PairU8Shape& s, const int32_t* rows,
+                              const uint16_t* offs) {
+  if (!pairu8_shape_ok(plan, s)) return set_error(DD_ERR_INVALID_ARG, "bad 8-bit pair shape");
+  const TileView tv(plan, s.td);
+  const int nch = plan->nchans;
+  const int npairs = (nch + 1) / 2;
+  const int nstage = (nch + s.cc - 1) / s.cc;
+  const int rw = 1 + 2 * s.rmax;
+  for (int tile = 0; tile < tv.ntiles; tile++) {
+    for (int st = 0; st < nstage; st++) {
+      const int32_t* rec = rows + (static_cast<size_t>(tile) * nstage + st) * rw;
+      const int nrows = rec[0];
+      const int c0 = st * s.cc, ncc = std::min(s.cc, nch - c0);
+      if (nrows < 1 || nrows > s.rmax) return set_error(DD_ERR_STATE, "8-bit pairs: row count");
+      for (int r = 0; r < nrows; r++)
+        if (rec[1 + 2 * r] < 0 || rec[1 + 2 * r] >= (ncc + 1) / 2)
+          return set_error(DD_ERR_STATE, "8-bit pairs: row of a pair outside the stage");
+      for (int pl = 0; pl < (ncc + 1) / 2; pl++) {
+        const int c = c0 + 2 * pl, g = c / 2;
+        const bool two = c + 1 < nch;
+        const int32_t a0 = tv.base[static_cast<size_t>(tile) * nch + c] & 3;
+        const int32_t a1 = two ? tv.base[static_cast<size_t>(tile) * nch + c + 1] & 3 : 0;
+        for (int q = 0; q < s.td; q++) {
+          const int32_t R = a0 + tv.rel(tile, q, c);
+          const int32_t d = two ? a1 + tv.rel(tile, q, c + 1) - R : 0;
+          const int64_t b = offs[(static_cast<size_t>(tile) * npairs + g) * s.td + q];
+          if (b % 4) return set_error(DD_ERR_STATE, "8-bit pairs: offset not a dword");
+          const int64_t dw = b / 4;
+          const int64_t copy = dw / s.slotp, at = dw % s.slotp;
+          const int64_t row = copy / 2;
+          if (row >= nrows) return set_error(DD_ERR_STATE, "8-bit pairs: offset past the rows");
+          if (rec[1 + 2 * row] != pl || rec[2 + 2 * row] != d)
+            return set_error(DD_ERR_STATE, "8-bit pairs: DM reads another pattern's row");
+          if (copy % 2 != (R & 1) || at != (R >> 1))
+            return set_error(DD_ERR_STATE, "8-bit pairs: wrong copy or dword");
+          if (at + 64 * s.idw > s.slotp)
+            return set_error(DD_ERR_STATE, "8-bit pairs: reads past the row");
+        }
+      }
+    }
+  }
+  return DD_OK;
+}
+
+dd_status plan_pairu8(dd_plan* plan, const PairU8Shape& s, const int32_t** rows,
+                      const int32_t** offs) {
+  int dev = 0;
+  DD_HIP(hipGetDevice(&dev));
+  const std::vector<int> key = {s.td, s.idw, s.slotp, s.cc, s.rmax};
+  {
+    std::lock_guard<std::mutex> lk(plan->mu);
+    auto& m = plan->dev[dev].pairu8;
+    auto it = m.find(key);
+    if (it != m.end()) {
+      *rows = it->second.first;
+      *offs = it->second.second;
+      return DD_OK;
+    }
+  }
+  std::vector<int32_t> hr;
+  std::vector<uint16_t> ho;
+  dd_status st = build_pairu8_tables(plan, s, &hr, &ho);
+  if (st != DD_OK) return st;
+  st = check_pairu8_tables(plan, s, hr.data(), ho.data());
+  if (st != DD_OK) return st;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  auto& m = plan->dev[dev].pairu8;
+  auto it = m.find(key);
+  if (it != m.end()) {
+    *rows = it->second.first;
+    *offs = it->second.second;
+    return DD_OK;
+  }
+  int32_t *dr = nullptr, *dofs = nullptr;
+  hipError_t err = hipMalloc(&dr, hr.size() * sizeof(int32_t));
+  if (err == hipSuccess) err = hipMalloc(&dofs, ho.size() * sizeof(uint16_t));
+  if (err == hipSuccess)
+    err = hipMemcpy(dr, hr.data(), hr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(dofs, ho.data(), ho.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(dr);
+    (void)hipFree(dofs);
+    return hip_error(err, "uploading the 8-bit pair tables");
+  }
+  m.emplace(key, std::make_pair(dr, dofs));
+  *rows = dr;
+  *offs = dofs;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 dd_plan::~dd_plan() {
@@ -686,6 +835,10 @@ dd_plan::~dd_plan() {
     for (auto& t : kv.second.wintab) (void)hipFree(t.second);
     for (auto& t : kv.second.jumptab) (void)hipFree(t.second);
     for (auto& t : kv.second.pairtab) {
+      (void)hipFree(t.second.first);
+      (void)hipFree(t.second.second);
+    }
+    for (auto& t : kv.second.pairu8) {
       (void)hipFree(t.second.first);
       (void)hipFree(t.second.second);
     }
