@@ -76,8 +76,10 @@ struct DeviceTables {
   // pair-sum entries and pattern records, keyed by the whole pair shape and
   // block layout (td, G, PMAX, slot, groups per stage, dw, k, np, pbs, rbs, end)
   std::map<std::vector<int>, std::pair<int32_t*, int32_t*>> pairtab;
-  // 8-bit pair-sum rows and offsets, keyed by (td, idw, slotp, cc, rmax)
+  // 8-bit pair-sum rows and offsets, keyed by (td, idw, slotp, cc, rmax),
+  // and the most rows any of their stages uses
   std::map<std::vector<int>, std::pair<int32_t*, int32_t*>> pairu8;
+  std::map<std::vector<int>, int> pairu8_used;
 };
 
 }  // namespace dd
@@ -227,6 +229,11 @@ dd_status plan_pairtab(dd_plan* plan, const PairShape& s, const LinkedLayout& L,
 // the pair's first channel.
 struct PairU8Shape {
   int td, idw, slotp, cc, rmax;  // idw: dwords per lane (two samples each)
+  // binary16 rows (variant 10): two samples per staged dword, one pattern
+  // row per (pair, pattern) with one output sample per dword (no shifted
+  // copy), offsets 4 * (row * slotp + R) with R = (base & 1) + rel, and idw
+  // samples (dwords) per lane
+  int half = 0;
 };
 constexpr int pairu8_raw_dwords(int slotp) { return (slotp / 2 + 2 + 63) & ~63; }
 dd_status build_pairu8_tables(const dd_plan* plan, const PairU8Shape& s,
@@ -236,8 +243,9 @@ dd_status build_pairu8_tables(const dd_plan* plan, const PairU8Shape& s,
 // and all its reads stay inside the row; at most rmax rows per stage.
 dd_status check_pairu8_tables(const dd_plan* plan, const PairU8Shape& s, const int32_t* rows,
                               const uint16_t* offs);
+// `used` (optional): the most pattern rows any stage of the plan needs.
 dd_status plan_pairu8(dd_plan* plan, const PairU8Shape& s, const int32_t** rows,
-                      const int32_t** offs);
+                      const int32_t** offs, int* used = nullptr);
 
 // Kernel launchers (dd_kernels.hip).
 struct ExecArgs {

@@ -47,6 +47,8 @@
 //                  tile that share a pair's delay pattern share its sum.
 //  9  BodyPairsU8: 8-bit input; 16-bit sums of channel pairs per delay
 //                  pattern, one v_add_u32 per two samples per pair and DM.
+// 10  BodyPairsF16: binary16 input; channel pairs packed per delay pattern,
+//                  one v_dot2_f32_f16 per sample per pair and DM.
 #include <cstring>
 #include <type_traits>
 
@@ -712,10 +714,11 @@ struct BodyPairsU8 {
     const int sp = (64 * IDW + (span_max + 3) / 2 + 1 + 63) & ~63;
     const int budget = 160 * 1024 / OCC / 4;  // dwords
     int c = max(2, cc_req & ~1);
-    // at least cc + 2 pattern rows per stage (about two per pair, and room
-    // for a stage whose pairs need a third)
-    while (c > 2 && rmax_for(sp, c, budget) < c + 2) c -= 2;
-    if (rmax_for(sp, c, budget) < c + 2) return -1;
+    // at least two pattern rows per pair of the stage; whether a plan's
+    // stages fit is decided when its tables are built (prepare tries
+    // smaller stages when they do not)
+    while (c > 2 && rmax_for(sp, c, budget) < c) c -= 2;
+    if (rmax_for(sp, c, budget) < c) return -1;
     *slot = sp;
     *cc = c;
     *lds = static_cast<size_t>(budget) * 4;
@@ -723,6 +726,177 @@ struct BodyPairsU8 {
   }
   static constexpr int table_epd = 0;
   static constexpr int pairu8_idw = IDW;
+};
+
+// --------------------------------------------------------------- variant 10
+//
+// Half-precision pair rows.  As variant 9, but a pattern row's dword t packs
+// the two channels' binary16 samples (x_c[t], x_c+1[t + d]), one output
+// sample per dword, so every DM reads aligned dwords without shifted copies,
+// and one v_dot2_f32_f16 against (1, 1) adds both channels into the FP32
+// accumulator (two channel-adds per instruction instead of one v_fma_mix
+// each).  Lane l owns the samples l + 64i, i < I.
+template <int DW, int I, int OCC_>
+struct BodyPairsF16 {
+  static constexpr int TD = 4 * DW, TT = 64 * I, OCC = OCC_;
+  static_assert(I % 2 == 0, "samples per lane come in read2 pairs");
+  __host__ __device__ static constexpr int raw_dwords(int slotp) { return (slotp / 2 + 3 + 63) & ~63; }
+  __host__ __device__ static constexpr int table_dwords(int cc) {
+    return ((cc + 1) / 2 * TD / 2 + 63) & ~63;
+  }
+  __host__ __device__ static constexpr int rmax_for(int slotp, int cc, int lds_dwords) {
+    return (lds_dwords - cc * raw_dwords(slotp) - 2 * table_dwords(cc)) / slotp;
+  }
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* lds = reinterpret_cast<uint32_t*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_id();
+    const unsigned char* in = static_cast<const unsigned char*>(p.in);
+    const int slotp = p.slot, cc = p.cc, slotr = raw_dwords(p.slot);
+    const int nstage = (p.nchans + cc - 1) / cc;
+    const int npairs = (p.nchans + 1) / 2;
+    const int rw = p.aux_w;
+    const int64_t row_bytes = p.in_stride * 2;
+    const int full_dwords = static_cast<int>(p.nsamp / 2);
+    const bool tail = (p.nsamp & 1) != 0;
+    const int tabd = table_dwords(cc);
+    uint32_t* raw = lds;
+    uint32_t* tabl = raw + cc * slotr;
+    uint32_t* pr = tabl + 2 * tabd;
+    auto window_dword = [&](int c) -> int {
+      return static_cast<int>((t0 + cload1(p.base + static_cast<int64_t>(dtile) * p.nchans + c)) >> 1);
+    };
+    auto issue = [&](int s, int buf) {
+      const int c0 = s * cc;
+      const int ncc = min(cc, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int gd = window_dword(c) - 1;  // one margin dword; -1 reads as zero
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<unsigned char*>(in + static_cast<int64_t>(c) * row_bytes), 0,
+            full_dwords * 4, 0x00020000);
+        uint32_t* dst = raw + i * slotr;
+        for (int e = 0; e < slotr; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
+      }
+      if (wave == 3) {  // the stage's DM offsets, [pair][TD] uint16
+        const int np = (ncc + 1) / 2;
+        const uint16_t* tp = reinterpret_cast<const uint16_t*>(p.tab) +
+                             (static_cast<int64_t>(dtile) * npairs + c0 / 2) * TD;
+        __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(tp), 0, np * TD * 2, 0x00020000);
+        uint32_t* dst = tabl + buf * tabd;
+        for (int e = 0; e < np * TD / 2; e += 64)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rt, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(e + lane) * 4u, 0, 0, 0);
+      }
+    };
+    // the half sample of an odd-length row's last dword
+    auto patch_tails = [&](int s) {
+      if (!tail) return;
+      const int c0 = s * cc;
+      const int ncc = min(cc, p.nchans - c0);
+      for (int i = wave; i < ncc; i += 4) {
+        const int c = c0 + i;
+        const int idx = full_dwords - (window_dword(c) - 1);
+        if (lane == 0 && idx >= 0 && idx < slotr) {
+          const uint16_t* rp = reinterpret_cast<const uint16_t*>(in + static_cast<int64_t>(c) * row_bytes);
+          raw[i * slotr + idx] = static_cast<uint32_t>(rp[2 * static_cast<int64_t>(full_dwords)]);
+        }
+      }
+    };
+    auto build = [&](int s) {
+      const int32_t* rec = p.aux + (static_cast<int64_t>(dtile) * nstage + s) * rw;
+      const int nrows = cload1(rec);
+      const int units = slotp / 2;
+      const int c0 = s * cc;
+      for (int row = wave; row < nrows; row += 4) {
+        const int pl = cload1(rec + 1 + 2 * row);
+        const int d = cload1(rec + 2 + 2 * row);
+        const bool two = c0 + 2 * pl + 1 < p.nchans;
+        const uint32_t* xr = raw + (2 * pl) * slotr + 1;  // + margin dword
+        const uint32_t* yr = raw + (2 * pl + 1) * slotr;
+        uint32_t* r0 = pr + row * slotp;
+        for (int u = lane; u < units; u += 64) {
+          const uint32_t x = xr[u];  // samples 2u, 2u+1 of channel c
+          uint32_t y = 0;
+          if (two) {
+            // samples 2u + d, 2u + d + 1 of channel c+1, kept inside the row
+            // (only units that no DM reads are ever clamped)
+            const int i0 = min(max(u + (d >> 1) + 1, 0), slotr - 2);
+            y = __builtin_amdgcn_alignbyte(yr[i0 + 1], yr[i0], static_cast<unsigned>(2 * (d & 1)));
+          }
+          *reinterpret_cast<uint2*>(r0 + 2 * u) =
+              make_uint2(__builtin_amdgcn_perm(y, x, 0x05040100u),
+                         __builtin_amdgcn_perm(y, x, 0x07060302u));
+        }
+      }
+    };
+    float acc[DW][I];
+#pragma unroll
+    for (int j = 0; j < DW; j++)
+#pragma unroll
+      for (int i = 0; i < I; i++) acc[j][i] = 0.f;
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 ones = {static_cast<_Float16>(1.0f), static_cast<_Float16>(1.0f)};
+    issue(0, 0);
+    for (int s = 0; s < nstage; s++) {
+      const int buf = s & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      patch_tails(s);
+      __syncthreads();  // raw rows of stage s landed; every wave is done with stage s-1's rows
+      build(s);
+      __syncthreads();  // pattern rows of stage s ready; the raw area is free
+      if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+      const int np = (min(cc, p.nchans - s * cc) + 1) / 2;
+      const uint32_t* tb = tabl + buf * tabd + wave * (DW / 2);
+      for (int pl = 0; pl < np; pl++) {
+        uint32_t w[DW / 2];
+#pragma unroll
+        for (int k = 0; k < DW / 2; k++) w[k] = tb[pl * (TD / 2) + k];
+#pragma unroll
+        for (int j = 0; j < DW; j++) {
+          const unsigned off = (w[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+          const uint32_t* src =
+              reinterpret_cast<const uint32_t*>(reinterpret_cast<const unsigned char*>(pr) + off) + lane;
+#pragma unroll
+          for (int i = 0; i < I; i++) {
+            const uint32_t v = src[64 * i];
+            acc[j][i] = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, v), ones, acc[j][i], false);
+          }
+        }
+      }
+    }
+    float* out = static_cast<float*>(p.out);
+#pragma unroll
+    for (int j = 0; j < DW; j++) {
+      const int row = p.rows[dtile * TD + wave * DW + j];
+      if (row < 0) continue;
+      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+      for (int i = 0; i < I; i++) {
+        const int64_t t = t0 + lane + 64 * i;
+        if (t < p.nout) o[t] = acc[j][i];
+      }
+    }
+  }
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    // a DM's first dword is R <= span_max + 1; it reads 64*I dwords
+    const int sp = (64 * I + span_max + 2 + 63) & ~63;
+    const int budget = 160 * 1024 / OCC / 4;  // dwords
+    int c = max(2, cc_req & ~1);
+    while (c > 2 && rmax_for(sp, c, budget) < c) c -= 2;
+    if (rmax_for(sp, c, budget) < c) return -1;
+    *slot = sp;
+    *cc = c;
+    *lds = static_cast<size_t>(budget) * 4;
+    return 0;
+  }
+  static constexpr int table_epd = 0;
+  static constexpr int pairf16_i = I;
 };
 
 // ---------------------------------------------------------------- variant 3
@@ -1346,7 +1520,8 @@ struct Impl {
   int td, tt, table_epd, table_ralign, table_win;
   JumpLayout table_jump;  // dw == 0: not a threaded-jump body
   int pair_g, pair_pmax, pair_nraw;  // pair_g == 0: not a pair-sum body
-  int pairu8_idw;                    // 0: not an 8-bit pair-sum body
+  int pairu8_idw;                    // 0: not an 8-bit or binary16 pair-row body
+  int pair_half;                     // 1: binary16 pair rows
   int (*pairu8_rmax)(int slotp, int cc, int lds_dwords);
   LinkedLayout table_pair;
   size_t in_size;
@@ -1402,6 +1577,17 @@ struct PairU8Of<Body, std::void_t<decltype(Body::pairu8_idw)>> {
   static int rmax(int slotp, int cc, int lds_dwords) { return Body::rmax_for(slotp, cc, lds_dwords); }
 };
 
+template <class Body, class = void>
+struct PairF16Of {
+  static constexpr int i = 0;
+  static int rmax(int, int, int) { return 0; }
+};
+template <class Body>
+struct PairF16Of<Body, std::void_t<decltype(Body::pairf16_i)>> {
+  static constexpr int i = Body::pairf16_i;
+  static int rmax(int slotp, int cc, int lds_dwords) { return Body::rmax_for(slotp, cc, lds_dwords); }
+};
+
 template <class Body, typename Tin>
 Impl make_impl() {
   Impl m;
@@ -1419,9 +1605,15 @@ Impl make_impl() {
   m.pair_nraw = PairOf<Body>::nraw;
   m.pairu8_idw = PairU8Of<Body>::idw;
   m.pairu8_rmax = &PairU8Of<Body>::rmax;
+  m.pair_half = 0;
+  if (PairF16Of<Body>::i) {  // the binary16 pair rows share the 8-bit tables' machinery
+    m.pairu8_idw = PairF16Of<Body>::i;
+    m.pairu8_rmax = &PairF16Of<Body>::rmax;
+    m.pair_half = 1;
+  }
   m.table_pair = PairOf<Body>::layout;
   m.in_size = sizeof(Tin);
-  m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0 || PairU8Of<Body>::idw != 0;
+  m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0 || m.pairu8_idw != 0;
   return m;
 }
 
@@ -1501,6 +1693,13 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
   }
   if (in_t == DD_U8 && v == 9) {
     if (d == 8 && k == 16) return *out = make_impl<BodyPairsU8<8, 8, 4>, uint8_t>(), true;
+    if (d == 8 && k == 8) return *out = make_impl<BodyPairsU8<8, 4, 6>, uint8_t>(), true;
+    if (d == 16 && k == 8) return *out = make_impl<BodyPairsU8<16, 4, 4>, uint8_t>(), true;
+    if (d == 16 && k == 16) return *out = make_impl<BodyPairsU8<16, 8, 3>, uint8_t>(), true;
+    if (d == 4 && k == 16) return *out = make_impl<BodyPairsU8<4, 8, 6>, uint8_t>(), true;
+    if (d == 8 && k == 4) return *out = make_impl<BodyPairsU8<8, 2, 8>, uint8_t>(), true;
+    if (d == 8 && k == 12) return *out = make_impl<BodyPairsU8<8, 6, 3>, uint8_t>(), true;
+    if (d == 16 && k == 4) return *out = make_impl<BodyPairsU8<16, 2, 6>, uint8_t>(), true;
   }
   if (in_t == DD_U8 && v == 4) {
     if (d == 8 && k == 28)
@@ -1526,6 +1725,12 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
     if (d == 4 && k == 12)
       return *out = make_impl<BodyWinX<_Float16, 4, 12, 40, 4, float, dd_f32_d4_k12_w40_channel>,
                               _Float16>(), true;
+  }
+  if (in_t == DD_F16 && v == 10) {
+    if (d == 8 && k == 8) return *out = make_impl<BodyPairsF16<8, 8, 5>, _Float16>(), true;
+    if (d == 8 && k == 4) return *out = make_impl<BodyPairsF16<8, 4, 6>, _Float16>(), true;
+    if (d == 16 && k == 4) return *out = make_impl<BodyPairsF16<16, 4, 4>, _Float16>(), true;
+    if (d == 8 && k == 16) return *out = make_impl<BodyPairsF16<8, 16, 3>, _Float16>(), true;
   }
   if (in_t == DD_F16 && v == 3) {
     if (d == 8 && k == 8) return *out = make_impl<BodyCopies<_Float16, 8, 4, 5>, _Float16>(), true;
@@ -1568,14 +1773,33 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
   const int32_t* aux = nullptr;
   int aux_w = 0;
   if (impl.pairu8_idw) {
-    const int rmax = impl.pairu8_rmax(slot, cc, static_cast<int>(lds / 4));
-    const PairU8Shape ps{impl.td, impl.pairu8_idw, slot, cc, rmax};
-    st = plan_pairu8(a.plan, ps, &aux, &tab);
+    // the largest stage (channels per stage, even) whose every (tile, stage)
+    // fits its pattern rows in the LDS left beside the raw rows
+    int rmax = 0, used = 0;
+    for (;;) {
+      rmax = impl.pairu8_rmax(slot, cc, static_cast<int>(lds / 4));
+      const PairU8Shape ps{impl.td, impl.pairu8_idw, slot, cc, rmax, impl.pair_half};
+      st = plan_pairu8(a.plan, ps, &aux, &tab, &used);
+      if (st != DD_ERR_NOT_IMPLEMENTED || cc <= 2) break;
+      if (impl.geometry(tt->span_max, cc - 2, &slot, &cc, &lds) != 0) break;
+    }
+    // LDS for the rows the plan's stages use, not the whole share: a smaller
+    // footprint lets more workgroups share a CU
+    if (st == DD_OK) {
+      const int rmax_all = rmax;
+      const int row_dw = (impl.pair_half ? 1 : 2) * slot;  // LDS dwords of one pattern row
+      while (rmax > used &&
+             impl.pairu8_rmax(slot, cc, static_cast<int>(lds / 4) - row_dw) >= used) {
+        lds -= static_cast<size_t>(row_dw) * 4;
+        rmax = impl.pairu8_rmax(slot, cc, static_cast<int>(lds / 4));
+      }
+      rmax = rmax_all;  // the record width the tables were built with
+    }
     if (st == DD_ERR_NOT_IMPLEMENTED) {
       // some stage needs more pattern rows than fit: the aligned-copies kernel
       TileShape s3 = s;
       s3.variant = 3;
-      s3.tsamp_per_lane = 16;
+      s3.tsamp_per_lane = impl.pair_half ? 8 : 16;
       return prepare(s3, in_t, a, out);
     }
     if (st != DD_OK) return st;
@@ -1692,8 +1916,18 @@ dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams
     PreparedLaunch pl;
     dd_status st = prepare(s, in_t, beams[i], &pl);
     if (st != DD_OK) return st;
-    if (i > 0 && pl.impl.batch != impl.batch)
+    if (i > 0 && pl.impl.batch != impl.batch) {
+      // a pair-sum shape that some beams' tables do not fit: the whole batch
+      // takes the kernel those beams fall back to (one kernel per batch)
+      if (s.variant == 8 || s.variant == 9 || s.variant == 10) {
+        TileShape f = s;
+        f.variant = s.variant == 8 ? 7 : 3;
+        if (s.variant == 9) f.tsamp_per_lane = 16;
+        if (s.variant == 10) f.tsamp_per_lane = 8;
+        return batch_prepare(f, in_t, beams, n, out);
+      }
       return set_error(DD_ERR_TOO_LARGE, "beams need different kernels for this shape");
+    }
     impl = pl.impl;
     std::memcpy(out->params.data() + static_cast<size_t>(i) * sizeof(KParams), &pl.p,
                 sizeof(KParams));

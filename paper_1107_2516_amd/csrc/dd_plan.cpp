@@ -696,8 +696,9 @@ dd_status build_pairu8_tables(const dd_plan* plan, const PairU8Shape& s,
       for (int pl = 0; pl < (ncc + 1) / 2; pl++) {
         const int c = c0 + 2 * pl, g = c / 2;
         const bool two = c + 1 < nch;
-        const int32_t a0 = tv.base[static_cast<size_t>(tile) * nch + c] & 3;
-        const int32_t a1 = two ? tv.base[static_cast<size_t>(tile) * nch + c + 1] & 3 : 0;
+        const int32_t am = s.half ? 1 : 3;  // samples per staged dword - 1
+        const int32_t a0 = tv.base[static_cast<size_t>(tile) * nch + c] & am;
+        const int32_t a1 = two ? tv.base[static_cast<size_t>(tile) * nch + c + 1] & am : 0;
         pat.clear();
         for (int q = 0; q < s.td; q++) {
           R0[q] = a0 + tv.rel(tile, q, c);
@@ -711,7 +712,8 @@ dd_status build_pairu8_tables(const dd_plan* plan, const PairU8Shape& s,
           const int row = nrows + static_cast<int>(std::find(pat.begin(), pat.end(), d1[q]) -
                                                    pat.begin());
           const int64_t b =
-              4 * ((static_cast<int64_t>(row) * 2 + (R0[q] & 1)) * s.slotp + (R0[q] >> 1));
+              s.half ? 4 * (static_cast<int64_t>(row) * s.slotp + R0[q])
+                     : 4 * ((static_cast<int64_t>(row) * 2 + (R0[q] & 1)) * s.slotp + (R0[q] >> 1));
           if (b > 0xffff) return set_error(DD_ERR_TOO_LARGE, "pattern row offset beyond 16 bits");
           (*offs)[(static_cast<size_t>(tile) * npairs + g) * s.td + q] = static_cast<uint16_t>(b);
         }
@@ -747,8 +749,9 @@ dd_status check_pairu8_tables(const dd_plan* plan, const PairU8Shape& s, const i
       for (int pl = 0; pl < (ncc + 1) / 2; pl++) {
         const int c = c0 + 2 * pl, g = c / 2;
         const bool two = c + 1 < nch;
-        const int32_t a0 = tv.base[static_cast<size_t>(tile) * nch + c] & 3;
-        const int32_t a1 = two ? tv.base[static_cast<size_t>(tile) * nch + c + 1] & 3 : 0;
+        const int32_t am = s.half ? 1 : 3;
+        const int32_t a0 = tv.base[static_cast<size_t>(tile) * nch + c] & am;
+        const int32_t a1 = two ? tv.base[static_cast<size_t>(tile) * nch + c + 1] & am : 0;
         for (int q = 0; q < s.td; q++) {
           const int32_t R = a0 + tv.rel(tile, q, c);
           const int32_t d = two ? a1 + tv.rel(tile, q, c + 1) - R : 0;
@@ -756,11 +759,11 @@ dd_status check_pairu8_tables(const dd_plan* plan, const PairU8Shape& s, const i
           if (b % 4) return set_error(DD_ERR_STATE, "8-bit pairs: offset not a dword");
           const int64_t dw = b / 4;
           const int64_t copy = dw / s.slotp, at = dw % s.slotp;
-          const int64_t row = copy / 2;
+          const int64_t row = s.half ? copy : copy / 2;
           if (row >= nrows) return set_error(DD_ERR_STATE, "8-bit pairs: offset past the rows");
           if (rec[1 + 2 * row] != pl || rec[2 + 2 * row] != d)
             return set_error(DD_ERR_STATE, "8-bit pairs: DM reads another pattern's row");
-          if (copy % 2 != (R & 1) || at != (R >> 1))
+          if (s.half ? at != R : (copy % 2 != (R & 1) || at != (R >> 1)))
             return set_error(DD_ERR_STATE, "8-bit pairs: wrong copy or dword");
           if (at + 64 * s.idw > s.slotp)
             return set_error(DD_ERR_STATE, "8-bit pairs: reads past the row");
@@ -772,10 +775,19 @@ dd_status check_pairu8_tables(const dd_plan* plan, const PairU8Shape& s, const i
 }
 
 dd_status plan_pairu8(dd_plan* plan, const PairU8Shape& s, const int32_t** rows,
-                      const int32_t** offs) {
+                      const int32_t** offs, int* used) {
   int dev = 0;
   DD_HIP(hipGetDevice(&dev));
-  const std::vector<int> key = {s.td, s.idw, s.slotp, s.cc, s.rmax};
+  const std::vector<int> key = {s.td, s.idw, s.slotp, s.cc, s.rmax, s.half};
+  auto most_rows = [&](const int32_t* hr) {
+    // largest row count over the (tile, stage) records
+    const size_t rw = 1 + 2 * static_cast<size_t>(s.rmax);
+    const size_t nrec = static_cast<size_t>((plan->ndms + s.td - 1) / s.td) *
+                        ((plan->nchans + s.cc - 1) / s.cc);
+    int m = 0;
+    for (size_t r = 0; r < nrec; r++) m = std::max(m, static_cast<int>(hr[r * rw]));
+    return m;
+  };
   {
     std::lock_guard<std::mutex> lk(plan->mu);
     auto& m = plan->dev[dev].pairu8;
@@ -783,6 +795,7 @@ dd_status plan_pairu8(dd_plan* plan, const PairU8Shape& s, const int32_t** rows,
     if (it != m.end()) {
       *rows = it->second.first;
       *offs = it->second.second;
+      if (used) *used = plan->dev[dev].pairu8_used[key];
       return DD_OK;
     }
   }
@@ -792,14 +805,18 @@ dd_status plan_pairu8(dd_plan* plan, const PairU8Shape& s, const int32_t** rows,
   if (st != DD_OK) return st;
   st = check_pairu8_tables(plan, s, hr.data(), ho.data());
   if (st != DD_OK) return st;
+  const int nused = most_rows(hr.data());
   std::lock_guard<std::mutex> lk(plan->mu);
   auto& m = plan->dev[dev].pairu8;
   auto it = m.find(key);
   if (it != m.end()) {
     *rows = it->second.first;
     *offs = it->second.second;
+    if (used) *used = plan->dev[dev].pairu8_used[key];
     return DD_OK;
   }
+  plan->dev[dev].pairu8_used[key] = nused;
+  if (used) *used = nused;
   int32_t *dr = nullptr, *dofs = nullptr;
   hipError_t err = hipMalloc(&dr, hr.size() * sizeof(int32_t));
   if (err == hipSuccess) err = hipMalloc(&dofs, ho.size() * sizeof(uint16_t));

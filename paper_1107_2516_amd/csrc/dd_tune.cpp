@@ -61,16 +61,16 @@ std::vector<TileShape> candidates(dd_dtype in_t) {
     return {make(7, 6, 12, 4), make(7, 8, 12, 8), make(6, 8, 12, 8), make(5, 8, 12, 8),
             make(7, 4, 12, 4), make(5, 8, 20, 6), make(1, 8, 12, 8), make(0, 8, 8, 8)};
   if (in_t == DD_U8)
-    return {make(3, 8, 16, 8), make(3, 8, 8, 8), make(3, 8, 16, 4), make(3, 4, 16, 8),
-            make(4, 8, 20, 8), make(4, 8, 28, 8), make(4, 4, 28, 8), make(0, 8, 8, 8)};
-  return {make(3, 8, 8, 8), make(3, 8, 4, 8), make(4, 8, 12, 8), make(4, 8, 20, 6),
-          make(0, 8, 8, 8)};
+    return {make(9, 8, 8, 4),  make(9, 16, 8, 4), make(9, 8, 16, 4), make(9, 8, 12, 4),
+            make(3, 8, 16, 8), make(3, 8, 16, 4), make(3, 8, 8, 8),  make(0, 8, 8, 8)};
+  return {make(10, 8, 8, 4), make(10, 8, 4, 4), make(3, 8, 8, 8), make(3, 8, 4, 8),
+          make(4, 8, 12, 8), make(0, 8, 8, 8)};
 }
 
 TileShape builtin_default(dd_dtype in_t) {
   if (in_t == DD_F32) return make(7, 6, 12, 4);  // shared windows, threaded jumps, 4 waves/SIMD
-  if (in_t == DD_U8) return make(3, 8, 16, 8);   // aligned copies, 16 samples per lane
-  return make(3, 8, 8, 8);                        // aligned-copies kernel
+  if (in_t == DD_U8) return make(9, 8, 8, 4);    // pair sums, 8 samples per lane
+  return make(10, 8, 8, 4);                       // binary16 pair rows
 }
 
 void load_file_locked() {

@@ -192,7 +192,8 @@ def test_batch_set_tile_every_u8_shape():
         buf[:, :x.shape[1]].copy_(torch.from_numpy(x))
         xs.append(buf[:, :x.shape[1]])
     b = dd.Batch([(p, x, None) for p, x in zip(plans, xs)])
-    for tile in [dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=8),
+    for tile in [dict(variant=9, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=4),
+                 dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=16, chans_per_stage=8),
                  dict(variant=3, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=4),
                  dict(variant=4, dms_per_wave=8, waves=4, tsamp_per_lane=20, chans_per_stage=8),
                  dict(variant=0, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=8)]:

@@ -59,6 +59,22 @@ def test_pairs_u8_bit_exact(nchans, ndms, step, extra, pad):
     assert np.array_equal(y9.cpu().numpy().astype(np.int64), oracle.dedisperse(x, tab))
 
 
+@pytest.mark.parametrize("dw,k", [(8, 8), (16, 8), (16, 16), (4, 16), (8, 4), (16, 4), (8, 12)])
+def test_pairs_u8_every_shape(dw, k):
+    """Every shape of the kernel (DMs per wavefront, samples per lane) on an
+    odd channel count with ragged DM and time tiles and padded rows."""
+    b = synth.Band(1023, 1510.0, 296.0 / 1023, 64e-6)
+    dms = synth.dm_grid(1000, 0.5)
+    tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, dms)
+    g = np.random.default_rng(dw * 100 + k)
+    x = _u8(g, (b.nchans, int(tab.max()) + 2345))
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, dms)
+    tile = dict(variant=9, dms_per_wave=dw, waves=4, tsamp_per_lane=k, chans_per_stage=8)
+    y = plan.execute_tiled(_pitched(x, 2), tile)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy().astype(np.int64), oracle.dedisperse(x, tab))
+
+
 def test_pairs_u8_saturated_input():
     """All samples 255 at 1024 channels: every 16-bit lane reaches 128 * 510
     before it is emptied, and every output is 255 * 1024 exactly."""
