@@ -136,11 +136,12 @@ struct JumpLayout {
 constexpr JumpLayout jump_layout(int dw, int k, int wmax) {
   return JumpLayout{dw, k, wmax, wmax - k + 1, 4 * k + 12, 8 + 2 * wmax + 4 + 8 + 4 * k + 12};
 }
-// Shared-window flavour (FP32 variant 7): window of 4k samples, plain blocks
-// padded to 8k + 12 bytes (up to k DPP adds of 8 bytes), reload blocks with
-// k/2 window reads and k DPP moves.  Same entries, builder and checker.
+// Shared-window flavour (FP32 variant 7): window of 4k samples, the last k
+// read from the next lane by DPP; plain blocks padded to 8k + 12 bytes (up to
+// k DPP adds of 8 bytes), reload blocks with 3k/4 window reads.  Same
+// entries, builder and checker.
 constexpr JumpLayout shared_jump_layout(int dw, int k) {
-  return JumpLayout{dw, k, 4 * k, 3 * k + 1, 8 * k + 12, 8 + 4 * k + 4 + 8 + 8 * k + 4 + 4 * k + 12};
+  return JumpLayout{dw, k, 4 * k, 3 * k + 1, 8 * k + 12, 8 + 6 * k + 4 + 8 + 4 * k + 12};
 }
 // Entries for ngroups groups of dw DMs from their shifts rel[g*dw + j]
 // relative to the staged window (>= 0): DM 0 reloads at rel & ~3, a later DM

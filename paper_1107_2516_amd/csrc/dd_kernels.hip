@@ -316,6 +316,139 @@ struct BodyWin {
                 "shared windows: threaded-jump step, window 4K, two supplying lanes");
 };
 
+// ------------------------------------------------------- variant 7 (stages)
+//
+// The shared-window threaded-jump step with the channel loop inside the
+// assembly: a call runs every channel of one stage.  On gfx950 a CU issues
+// about one scalar instruction per clock against two vector adds, so the
+// scalar work around each channel (loop control, table addressing, entry
+// hand-over, staging address arithmetic) set the pace of the per-channel
+// step; here it is cut to the jumps, DW 64-bit entry moves and three loop
+// instructions per channel.  Staging copies 16 bytes per lane per DMA
+// instruction (buffer_load_dwordx4 ... lds writes each lane's 16 bytes
+// contiguously, and its range check is per dword, so the last partial vector
+// of a row keeps its in-range samples and zero-fills the rest), four
+// instructions per M0 value through immediate offsets; slots are whole
+// multiples of 256 samples so that no copy spills into the next channel's.
+// Each wave's channel offset for the next stage is read a stage ahead.  The
+// blocks, table layout and entries are variant 7's, so the arithmetic and its
+// order are the same and so are the results, bit for bit.
+template <int DW, int K, int OCC_,
+          void (*STEP)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned*, int),
+          int (*FAST)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned*, int)>
+struct BodyWinStage {
+  static constexpr int TD = 4 * DW, LANES = 62, TT = LANES * K, OCC = OCC_, WMAX = 4 * K;
+  __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* lds = reinterpret_cast<float*>(smem);
+    const int64_t t0 = static_cast<int64_t>(ttile) * TT;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_id();
+    const float* in = static_cast<const float*>(p.in);
+    const int slot = p.slot;  // multiple of 256 samples
+    const int cc_max = p.cc;
+    const int nstage = (p.nchans + cc_max - 1) / cc_max;
+    const int row_bytes = static_cast<int>(p.nsamp * 4);
+    const unsigned lane_addr = static_cast<unsigned>(reinterpret_cast<uintptr_t>(lds)) +
+                               static_cast<unsigned>(lane * K * 4);
+    const int32_t* basew = p.base + static_cast<int64_t>(dtile) * p.nchans;
+    const int slot_hi = slot & ~1023, rem = (slot >> 8) & 3;
+    // one channel row into LDS: whole groups of four 16-byte DMA instructions
+    // per M0 value, then the remaining one to three
+    auto dma_row = [&](const float* row, float* dst, int g0) {
+      __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), 0, row_bytes, 0x00020000);
+      const unsigned voff = static_cast<unsigned>(g0 + 4 * lane) * 4u;
+#pragma unroll 1
+      for (int e = 0; e < slot_hi; e += 1024) {
+        lds_void_t* d = (lds_void_t*)(dst + e);
+        const unsigned v = voff + static_cast<unsigned>(e) * 4u;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 1024, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 2048, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 3072, 0);
+      }
+      if (rem) {
+        lds_void_t* d = (lds_void_t*)(dst + slot_hi);
+        const unsigned v = voff + static_cast<unsigned>(slot_hi) * 4u;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 0, 0);
+        if (rem > 1) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 1024, 0);
+        if (rem > 2) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 2048, 0);
+      }
+    };
+    // this wave's first channel of each stage, a stage ahead: its row, its
+    // slot in either buffer and its window offset
+    const float* rowp = in + static_cast<int64_t>(wave) * p.in_stride;
+    const int64_t rstep = static_cast<int64_t>(cc_max) * p.in_stride;
+    float* dst0 = lds + wave * slot;
+    float* dst1 = dst0 + cc_max * slot;
+    int gb_next = wave < min(cc_max, p.nchans) ? cload1(basew + wave) : 0;
+    auto issue = [&](int s, int buf) {
+      const int c0 = s * cc_max;
+      const int ncc = min(cc_max, p.nchans - c0);
+      if (wave < ncc) dma_row(rowp, buf ? dst1 : dst0, static_cast<int>(t0) + gb_next);
+      for (int i = wave + 4; i < ncc; i += 4) {  // stages of more than four channels
+        const int c = c0 + i;
+        dma_row(in + static_cast<int64_t>(c) * p.in_stride, lds + (buf * cc_max + i) * slot,
+                static_cast<int>(t0) + cload1(basew + c));
+      }
+      rowp += rstep;
+      const int cn = c0 + cc_max + wave;
+      if (cn < p.nchans && wave < cc_max) gb_next = cload1(basew + cn);
+    };
+    float acc[DW * K];
+#pragma unroll
+    for (int i = 0; i < DW * K; i++) acc[i] = 0.f;
+    const int32_t* tabw =
+        uniform_ptr(p.tab + static_cast<int64_t>(dtile) * p.nchans * TD * 2 + wave * DW * 2);
+    int2v e[DW];
+    {
+      int r[2 * DW];
+      cload_dw<2 * DW>(tabw, r);
+#pragma unroll
+      for (int i = 0; i < DW; i++) e[i] = int2v{r[2 * i], r[2 * i + 1]};
+    }
+    unsigned toff = TD * 2 * 4;  // bytes from tabw to the next channel's entries
+    issue(0, 0);
+    for (int s = 0; s < nstage; s++) {
+      const int buf = s & 1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // stage s is in LDS; every wave is done with stage s-1
+      if (s + 1 < nstage) issue(s + 1, buf ^ 1);
+      const int ncc = min(cc_max, p.nchans - s * cc_max);
+      const unsigned a = lane_addr + static_cast<unsigned>(buf * cc_max * slot * 4);
+      if (!FAST(acc, e, a, static_cast<unsigned>(slot * 4), tabw, &toff, ncc - 1))
+        STEP(acc, e, a, static_cast<unsigned>(slot * 4), tabw, &toff, ncc - 1);
+    }
+    float* out = static_cast<float*>(p.out);
+#pragma unroll
+    for (int j = 0; j < DW; j++) {
+      const int row = p.rows[dtile * TD + wave * DW + j];
+      if (row < 0) continue;
+      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int64_t t = t0 + lane * K + k;
+        if (lane < LANES && t < p.nout) o[t] = acc[j * K + k];
+      }
+    }
+  }
+  static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
+    const int s = (TT + span_max + WMAX + 255) & ~255;
+    const size_t sb = static_cast<size_t>(s) * sizeof(float);
+    const size_t budget = 160 * 1024 / OCC;
+    if (2 * sb > budget) return -1;
+    int c = cc_req;
+    while (c > 1 && 2 * sb * c > budget) c--;
+    *slot = s;
+    *cc = c;
+    *lds = 2 * sb * c;
+    return 0;
+  }
+  static constexpr int table_epd = 0;
+  static constexpr JumpLayout table_jump = shared_jump_layout(DW, K);
+};
+
 // ---------------------------------------------------------------- variant 8
 //
 // Pair sums (exact sub-sum sharing) under the shared-window step.  Channels
@@ -1431,9 +1564,9 @@ DD_CHECK_LAYOUT(T_F32_D4_K12_W48, 4, 12, 48)
                     shared_jump_layout(DW, K).rbs == DD_##NAME##_RBS &&                \
                     shared_jump_layout(DW, K).wmax == DD_##NAME##_WMAX,                \
                 "shared-window layout differs from the generated blocks");
-DD_CHECK_SHARED(W_F32_D8_K12, 8, 12)
-DD_CHECK_SHARED(W_F32_D6_K12, 6, 12)
-DD_CHECK_SHARED(W_F32_D4_K12, 4, 12)
+DD_CHECK_SHARED(V_F32_D8_K12, 8, 12)
+DD_CHECK_SHARED(V_F32_D6_K12, 6, 12)
+DD_CHECK_SHARED(V_F32_D4_K12, 4, 12)
 #undef DD_CHECK_SHARED
 static_assert(linked_layout(6, 12).np == DD_L_F32_D6_K12_NP &&
                   linked_layout(6, 12).pbs == DD_L_F32_D6_K12_PBS &&
@@ -1665,13 +1798,16 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
   }
   if (in_t == DD_F32 && v == 7) {
     if (d == 8 && k == 12)
-      return *out = make_impl<BodyWin<8, 12, 48, 3, dd_w_f32_d8_k12_channel, false, true, 62>,
+      return *out = make_impl<BodyWinStage<8, 12, 3, dd_v_f32_d8_k12_stage,
+                                           dd_v_f32_d8_k12_stagef>,
                               float>(), true;
     if (d == 6 && k == 12)
-      return *out = make_impl<BodyWin<6, 12, 48, 4, dd_w_f32_d6_k12_channel, false, true, 62>,
+      return *out = make_impl<BodyWinStage<6, 12, 4, dd_v_f32_d6_k12_stage,
+                                           dd_v_f32_d6_k12_stagef>,
                               float>(), true;
     if (d == 4 && k == 12)
-      return *out = make_impl<BodyWin<4, 12, 48, 5, dd_w_f32_d4_k12_channel, false, true, 62>,
+      return *out = make_impl<BodyWinStage<4, 12, 5, dd_v_f32_d4_k12_stage,
+                                           dd_v_f32_d4_k12_stagef>,
                               float>(), true;
   }
   if (in_t == DD_F32 && v == 8) {

@@ -407,8 +407,10 @@ dd_status plan_jumptab(dd_plan* plan, int td, const JumpLayout& L, const int32_t
       }
     }
   }
-  // +16: a wavefront fetches its 2*dw words with one scalar load, one channel ahead
-  std::vector<int32_t> host(static_cast<size_t>(ngroups) * 2 * L.dw + 16, 0);
+  // a wavefront fetches its 2*dw words with one 16-word scalar load, one
+  // channel ahead, also past the last channel of the last tile: one channel
+  // row of padding plus 16 words
+  std::vector<int32_t> host(static_cast<size_t>(ngroups) * 2 * L.dw + 2 * td + 16, 0);
   st = build_jump_entries(rel.data(), ngroups, L, host.data());
   if (st != DD_OK) return st;
   st = check_jump_entries(host.data(), rel.data(), ngroups, L);

@@ -449,91 +449,133 @@ def gen_thread(name, dw, k, wmax, occ):
     return "\n".join(out)
 
 
-SHARED_CONFIGS = [
-    # shared-window flavour: name, DMs per wave, samples per lane, waves per SIMD
-    ("w_f32_d8_k12", 8, 12, 3),
-    ("w_f32_d6_k12", 6, 12, 4),
-    ("w_f32_d4_k12", 4, 12, 5),
-]
-
-
 def shared_layout(dw, k):
     """Byte layout of the shared-window block table: DW*NP plain blocks of PBS
     bytes, then DW*4 reload blocks of RBS bytes (window of 4K floats, NP =
-    3K+1 window offsets).
+    3K+1 window offsets).  A lane loads the first 3K samples of its window
+    from LDS; the last K are the next lane's samples 2K..3K-1 (lane l+1's
+    window starts K samples after lane l's), read by DPP.
 
-    plain block (j, o):  K adds (o+i < 2K: own registers, 4 B each;
-                         2K <= o+i < 3K: the neighbour's copy, 4 B;
+    plain block (j, o):  K adds (o+i < 3K: own registers, 4 B each;
                          3K <= o+i: DPP from the next lane, 8 B), then the jump
                          to DM j+1's block (12 B), padded with s_nop to the
                          largest block (8K + 12 B)
-    reload block (j, q): s_lshl_b32 + v_add_u32_e32, K/2 ds_read_b128,
+    reload block (j, q): v_lshl_add_u32 (8 B), 3K/4 ds_read_b128 (8 B each),
                          s_waitcnt, the scalar load of the next channel's
-                         entries on DM 0 (8 B) or two s_nop, K v_mov_b32_dpp
-                         (the next lane's second run), s_nop 1, K adds of
-                         registers q..q+K-1 and the jump"""
+                         entries on DM 0 (8 B) or two s_nop, K adds of
+                         registers q..q+K-1 (4 B each) and the jump"""
     np_ = 3 * k + 1
     pbs = 8 * k + 12
-    rbs = 8 + 8 * (k // 2) + 4 + 8 + 8 * k + 4 + 4 * k + 12
+    rbs = 8 + 8 * (3 * k // 4) + 4 + 8 + 4 * k + 12
     return np_, pbs, rbs
 
 
-def gen_shared(name, dw, k, occ):
-    """Shared-window flavour of the threaded-jump step.  Lanes' register
-    windows overlap: lane l's window of 4K samples starts K samples after lane
-    l-1's.  Each lane reads only the first 2K samples of its window from LDS
-    (run A); the next K come from lane l+1's second run (A[K..2K-1]) through
-    one DPP wavefront shift (run B, K v_mov_b32_dpp per window load), and the
-    last K from lane l+2, read by the adds themselves as DPP operands on B.
-    A window load thus costs half the LDS bytes of a private one.  Lanes 62
-    and 63 only supply data (their own sums are never stored), so a wave
-    owns 62*K output samples.  Block selection and table as gen_thread; the
-    table builder and checker are shared with it (window 4K, slack 3K)."""
+STAGE_CONFIGS = [
+    # shared-window step that runs a whole stage of channels: name, DMs per
+    # wave, samples per lane, waves per SIMD
+    ("v_f32_d8_k12", 8, 12, 3),
+    ("v_f32_d6_k12", 6, 12, 4),
+    ("v_f32_d4_k12", 4, 12, 5),
+]
+# the stage step keeps a channel's entries in SGPRs it names itself: the
+# current channel's 2*DW words from SA, the next channel's (scalar load
+# target, 16 words) from SB
+SA, SB = 56, 72
+
+
+def gen_stage(name, dw, k, occ, fast=False):
+    """Shared-window threaded-jump step that runs every channel of one stage.
+
+    A lane owns K consecutive output samples of DW trial DMs; lane l's window
+    of 4K staged samples starts K samples after lane l-1's.  For one channel
+    each DM's table entry names the block that adds its K-sample run at its
+    offset in the window (the offset is fixed in the block's code), and every
+    block ends by jumping straight to the next DM's block.  A DM whose run
+    lies outside the current window takes a reload block: it reads samples
+    0..3K-1 of the window from LDS (3K/4 ds_read_b128) at the DM's own start;
+    adds at window positions 3K..4K-1 read the next lane's positions 2K..3K-1
+    through a DPP wave shift.  Only plain VGPR-operand adds pair up across
+    the SIMD's two VALU pipes on gfx950 (DPP, SGPR-operand and three-source
+    forms issue on one pipe at half rate), so the window is loaded rather
+    than shifted into place, and DPP is left to the rare far offsets.
+
+    A scalar instruction also costs issue time (about one per CU per clock),
+    so the channel loop, the entry hand-over (DW s_mov_b64 from the scalar
+    load target SB to the live set SA), the LDS address and the table offset
+    advance are inside the assembly.
+
+    In: acc, the first channel's entries as DW SGPR pairs (returned holding
+    the entries of the channel after the stage), the first channel's LDS
+    address, the LDS stride between channels, the wavefront's table base and
+    the byte offset of the next channel's entries (advanced per channel), and
+    the channel count minus one.
+
+    fast: each jump is s_add_u32 + s_setpc_b64 (the high word of the target
+    is the table's, set once), which holds while no block offset carries out
+    of the low 32 bits of the table address.  The step checks that on entry
+    (the table's low word plus its size must not carry) and, if it would,
+    returns 0 at once having changed nothing, so the caller runs the plain
+    flavour; otherwise it returns 1."""
     assert k % 4 == 0 and 2 <= dw <= 8
-    wmax = 4 * k
-    # window registers at the top of the budget: A (2K) then B (K)
     wb = vgpr_budget(occ) - 3 * k
-    va, vb = wb, wb + 2 * k
+    va = wb
     np_, pbs, rbs = shared_layout(dw, k)
-    # the next channel's 2*DW entries with one scalar load (a wave's entries
-    # are followed by at least 16 words of table)
     nload = "s_load_dwordx8" if 2 * dw <= 8 else "s_load_dwordx16"
-    vec = "int8v" if 2 * dw <= 8 else "int16v"
+    nb = 8 if 2 * dw <= 8 else 16
     out = []
-    out.append(f"// {name}: DW={dw} K={k} OCC={occ}, run A v{va}..v{va + 2 * k - 1}, "
-               f"run B v{vb}..v{vb + k - 1}, {dw * np_} plain blocks of {pbs} B, "
-               f"{dw * 4} reload blocks of {rbs} B")
+    out.append(f"// {name}: DW={dw} K={k} OCC={occ}, window v{va}..v{va + 3 * k - 1}, "
+               f"entries s{SA}.. (next: s{SB}..), "
+               f"{dw * np_} plain blocks of {pbs} B, {dw * 4} reload blocks of {rbs} B")
     up = name.upper()
     out.append(f"#define DD_{up}_NP {np_}")
     out.append(f"#define DD_{up}_PBS {pbs}")
     out.append(f"#define DD_{up}_RBS {rbs}")
-    out.append(f"#define DD_{up}_WMAX {wmax}")
-    out.append(f"__device__ __forceinline__ void dd_{name}_channel(float* acc, const int* e, unsigned addr, const int32_t* next, int* en) {{")
-    out += ["  unsigned va;", f"  {vec} nv;"]
+    out.append(f"#define DD_{up}_WMAX {4 * k}")
+    table_bytes = dw * np_ * pbs + dw * 4 * rbs
+    sfx = "stagef" if fast else "stage"
+    ret = "int" if fast else "void"
+    out.append(f"__device__ __forceinline__ {ret} dd_{name}_{sfx}(float* acc, int2v* e, unsigned addr, "
+               f"unsigned lstride, const int32_t* tab, unsigned* toff, int cnt) {{")
+    out.append("  unsigned va;")
+    if fast:
+        out.append("  int ok;")
     out.append("  asm volatile(")
     out.append(f'      "s_getpc_b64 s[{TPC}:{TPC + 1}]\\n"')
     out.append('      ".Lpc%=:\\n"')
     out.append(f'      "s_add_u32 s{TPC}, s{TPC}, .Ltab%=-.Lpc%=\\n"')
     out.append(f'      "s_addc_u32 s{TPC + 1}, s{TPC + 1}, 0\\n"')
-    out.append(f'      "s_add_u32 s{TTG}, s{TPC}, %[o0]\\n"')
-    out.append(f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"')
+    if fast:
+        out.append('      "s_mov_b32 %[ok], 0\\n"')
+        out.append(f'      "s_add_u32 s{TTG}, s{TPC}, {table_bytes}\\n"')
+        out.append('      "s_cbranch_scc1 .Lout%=\\n"')
+        out.append('      "s_mov_b32 %[ok], 1\\n"')
+        out.append(f'      "s_mov_b32 s{TTG + 1}, s{TPC + 1}\\n"')
+    for i in range(dw):
+        out.append(f'      "s_mov_b64 s[{SA + 2 * i}:{SA + 2 * i + 1}], %[e{i}]\\n"')
+    out.append('      ".Lchan%=:\\n"')
+    out.append(f'      "s_add_u32 s{TTG}, s{TPC}, s{SA}\\n"')
+    if not fast:
+        out.append(f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"')
     out.append(f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"')
     out.append('      ".p2align 6\\n"')
     out.append('      ".Ltab%=:\\n"')
 
     def tail(j):
         if j < dw - 1:
-            return [f'      "s_add_u32 s{TTG}, s{TPC}, %[o{j + 1}]\\n"',
+            if fast:  # same 12 bytes; the s_nop after the jump never runs
+                return [f'      "s_add_u32 s{TTG}, s{TPC}, s{SA + j + 1}\\n"',
+                        f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"',
+                        '      "s_nop 0\\n"']
+            return [f'      "s_add_u32 s{TTG}, s{TPC}, s{SA + j + 1}\\n"',
                     f'      "s_addc_u32 s{TTG + 1}, s{TPC + 1}, 0\\n"',
                     f'      "s_setpc_b64 s[{TTG}:{TTG + 1}]\\n"']
-        return ['      "s_branch .Lend%=\\n"', '      "s_nop 0\\n"', '      "s_nop 0\\n"']
+        return ['      "s_branch .Lnext%=\\n"', '      "s_nop 0\\n"', '      "s_nop 0\\n"']
 
     def add(j, i, w):
-        if w < 2 * k:
-            return f'      "v_add_f32_e32 %[a{j}_{i}], v{va + w}, %[a{j}_{i}]\\n"', 4
         if w < 3 * k:
-            return f'      "v_add_f32_e32 %[a{j}_{i}], v{vb + w - 2 * k}, %[a{j}_{i}]\\n"', 4
-        return (f'      "v_add_f32_dpp %[a{j}_{i}], v{vb + w - 3 * k}, %[a{j}_{i}] '
+            return f'      "v_add_f32_e32 %[a{j}_{i}], v{va + w}, %[a{j}_{i}]\\n"', 4
+        # the next lane's window position w - K (its window starts K later)
+        return (f'      "v_add_f32_dpp %[a{j}_{i}], v{va + w - k}, %[a{j}_{i}] '
                 f'wave_shl:1 row_mask:0xf bank_mask:0xf\\n"', 8)
 
     def place(label, off):
@@ -556,40 +598,49 @@ def gen_shared(name, dw, k, occ):
     for j in range(dw):
         for q in range(4):
             out += place(f".Lr%=_{j}_{q}", base + (j * 4 + q) * rbs)
-            out.append(f'      "s_lshl_b32 s{TTG}, %[s{j}], 2\\n"')
-            out.append(f'      "v_add_u32_e32 %[va], s{TTG}, %[addr]\\n"')
-            for i in range(k // 2):
+            # window start (samples) * 4 + the channel's LDS address: 8 B
+            out.append(f'      "v_lshl_add_u32 %[va], s{SA + dw + j}, 2, %[addr]\\n"')
+            for i in range(3 * k // 4):
                 off = f" offset:{16 * i}" if i else ""
                 out.append(f'      "ds_read_b128 v[{va + 4 * i}:{va + 4 * i + 3}], %[va]{off}\\n"')
             out.append('      "s_waitcnt lgkmcnt(0)\\n"')
             if j == 0:
-                out.append(f'      "{nload} %[rn], %[tp], 0\\n"')
+                out.append(f'      "{nload} s[{SB}:{SB + nb - 1}], %[tp], %[toff]\\n"')
             else:
                 out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
-            for m in range(k):
-                out.append(f'      "v_mov_b32_dpp v{vb + m}, v{va + k + m} wave_shl:1 '
-                           f'row_mask:0xf bank_mask:0xf\\n"')
-            # a DPP read of a VGPR written by VALU needs two wait states
-            out.append('      "s_nop 1\\n"')
+            # q + i < K + 3 <= 3K: own registers only
             for i in range(k):
                 out.append(add(j, i, q + i)[0])
             out += tail(j)
-    out.append('      ".Lend%=:\\n"')
+    out.append('      ".Lnext%=:\\n"')
     out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+    for i in range(dw):
+        out.append(f'      "s_mov_b64 s[{SA + 2 * i}:{SA + 2 * i + 1}], s[{SB + 2 * i}:{SB + 2 * i + 1}]\\n"')
+    out.append('      "v_add_u32_e32 %[addr], %[ls], %[addr]\\n"')
+    out.append('      "s_add_u32 %[toff], %[toff], %[ts]\\n"')
+    out.append('      "s_sub_u32 %[cnt], %[cnt], 1\\n"')
+    out.append('      "s_cbranch_scc0 .Lchan%=\\n"')
+    for i in range(dw):
+        out.append(f'      "s_mov_b64 %[e{i}], s[{SA + 2 * i}:{SA + 2 * i + 1}]\\n"')
+    if fast:
+        out.append('      ".Lout%=:\\n"')
     outs = []
     for j in range(dw):
         for kk in range(k):
             outs.append(f'[a{j}_{kk}] "+v"(acc[{j * k + kk}])')
-    outs += ['[va] "=&v"(va)', '[rn] "=&s"(nv)']
-    ins = ['[addr] "v"(addr)', '[tp] "s"(next)']
-    ins += [f'[o{j}] "s"(e[{j}])' for j in range(dw)]
-    ins += [f'[s{j}] "s"(e[{dw + j}])' for j in range(dw)]
+    outs += ['[va] "=&v"(va)', '[addr] "+v"(addr)', '[toff] "+s"(*toff)', '[cnt] "+s"(cnt)']
+    if fast:
+        outs.append('[ok] "=&s"(ok)')
+    outs += [f'[e{i}] "+s"(e[{i}])' for i in range(dw)]
+    ins = ['[tp] "s"(tab)', '[ls] "s"(lstride)', f'[ts] "n"({4 * 2 * 4 * dw})']
     clob = [f'"v{wb + i}"' for i in range(3 * k)]
+    clob += [f'"s{i}"' for i in range(SA, SA + 2 * dw)] + [f'"s{i}"' for i in range(SB, SB + nb)]
     clob += [f'"s{i}"' for i in (TPC, TPC + 1, TTG, TTG + 1)] + ['"scc"', '"memory"']
     out.append("      : " + ",\n        ".join(outs))
     out.append("      : " + ", ".join(ins))
     out.append("      : " + ", ".join(clob) + ");")
-    out.append(f"  for (int i = 0; i < {2 * dw}; i++) en[i] = nv[i];")
+    if fast:
+        out.append("  return ok;")
     out.append("}")
     return "\n".join(out)
 
@@ -623,7 +674,8 @@ def gen_linked(name, dw, k, occ):
     The first block of a step is always a 'first visit' reload block, which
     issues the scalar load of the next step's entries once its window has
     arrived; other reload blocks do not.  Windows are shared between lanes
-    as in gen_shared (lanes 62 and 63 only supply data).  The host builds
+    by DPP (lane l+1's window starts K samples after lane l's; lanes 62 and
+    63 only supply data).  The host builds
     and checks every entry (plan_linkedtab)."""
     assert k % 4 == 0 and 2 <= dw <= 7  # 1 + 2*DW entries fit one s_load_dwordx16
     wmax = 4 * k
@@ -726,6 +778,7 @@ def gen_linked(name, dw, k, occ):
 def main():
     print("// Generated by gen_window_asm.py; do not edit by hand.")
     print("#pragma once")
+    print("typedef int int2v __attribute__((ext_vector_type(2)));")
     print("typedef int int4v __attribute__((ext_vector_type(4)));")
     print("typedef int int8v __attribute__((ext_vector_type(8)));")
     print("typedef int int16v __attribute__((ext_vector_type(16)));")
@@ -744,11 +797,13 @@ def main():
     for cfg in THREAD_CONFIGS:
         print(gen_thread(*cfg))
         print()
-    for cfg in SHARED_CONFIGS:
-        print(gen_shared(*cfg))
-        print()
     for cfg in LINKED_CONFIGS:
         print(gen_linked(*cfg))
+        print()
+    for cfg in STAGE_CONFIGS:
+        print(gen_stage(*cfg))
+        print()
+        print(gen_stage(*cfg, fast=True))
         print()
 
 
