@@ -272,6 +272,7 @@ struct BatchLaunch {
   size_t lds = 0;                     // dynamic LDS per workgroup (max over beams)
   const void* kernel = nullptr;
   int grid = 0;                       // persistent grid: CUs x resident workgroups per CU
+  int threads = 256;                  // per workgroup
 };
 dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
                         BatchLaunch* out);

@@ -333,11 +333,14 @@ struct BodyWin {
 // Each wave's channel offset for the next stage is read a stage ahead.  The
 // blocks, table layout and entries are variant 7's, so the arithmetic and its
 // order are the same and so are the results, bit for bit.
-template <int DW, int K, int OCC_,
-          void (*STEP)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned*, int),
-          int (*FAST)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned*, int)>
+template <int DW, int K, int OCC_, int WAVES,
+          void (*STEP)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned, unsigned*, int),
+          int (*FAST)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned, unsigned*, int)>
 struct BodyWinStage {
-  static constexpr int TD = 4 * DW, LANES = 62, TT = LANES * K, OCC = OCC_, WMAX = 4 * K;
+  static constexpr int TD = WAVES * DW, LANES = 62, TT = LANES * K, OCC = OCC_, WMAX = 4 * K;
+  static constexpr int THREADS = 64 * WAVES;
+  // a workgroup's wavefronts must fit the CU's 4 SIMDs at OCC waves each
+  static_assert(WAVES % 4 == 0 && WAVES <= 4 * OCC_, "workgroup does not fit a CU");
   __device__ __forceinline__ static void run(const KParams& p, int dtile, int ttile) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* lds = reinterpret_cast<float*>(smem);
@@ -387,7 +390,7 @@ struct BodyWinStage {
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
       if (wave < ncc) dma_row(rowp, buf ? dst1 : dst0, static_cast<int>(t0) + gb_next);
-      for (int i = wave + 4; i < ncc; i += 4) {  // stages of more than four channels
+      for (int i = wave + WAVES; i < ncc; i += WAVES) {  // more channels than wavefronts
         const int c = c0 + i;
         dma_row(in + static_cast<int64_t>(c) * p.in_stride, lds + (buf * cc_max + i) * slot,
                 static_cast<int>(t0) + cload1(basew + c));
@@ -417,8 +420,8 @@ struct BodyWinStage {
       if (s + 1 < nstage) issue(s + 1, buf ^ 1);
       const int ncc = min(cc_max, p.nchans - s * cc_max);
       const unsigned a = lane_addr + static_cast<unsigned>(buf * cc_max * slot * 4);
-      if (!FAST(acc, e, a, static_cast<unsigned>(slot * 4), tabw, &toff, ncc - 1))
-        STEP(acc, e, a, static_cast<unsigned>(slot * 4), tabw, &toff, ncc - 1);
+      if (!FAST(acc, e, a, static_cast<unsigned>(slot * 4), tabw, TD * 8, &toff, ncc - 1))
+        STEP(acc, e, a, static_cast<unsigned>(slot * 4), tabw, TD * 8, &toff, ncc - 1);
     }
     float* out = static_cast<float*>(p.out);
 #pragma unroll
@@ -436,7 +439,8 @@ struct BodyWinStage {
   static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
     const int s = (TT + span_max + WMAX + 255) & ~255;
     const size_t sb = static_cast<size_t>(s) * sizeof(float);
-    const size_t budget = 160 * 1024 / OCC;
+    // 4 * OCC wavefronts per CU share its 160 KB
+    const size_t budget = static_cast<size_t>(160 * 1024) * WAVES / (4 * OCC);
     if (2 * sb > budget) return -1;
     int c = cc_req;
     while (c > 1 && 2 * sb * c > budget) c--;
@@ -1576,8 +1580,18 @@ static_assert(linked_layout(6, 12).np == DD_L_F32_D6_K12_NP &&
 
 // ------------------------------------------------------------------ kernels
 
+// Threads per workgroup: 256 (four wavefronts) unless the body says otherwise.
+template <class Body, class = void>
+struct ThreadsOf {
+  static constexpr int value = 256;
+};
 template <class Body>
-__global__ __launch_bounds__(256, Body::OCC) void k_single(KParams p) {
+struct ThreadsOf<Body, std::void_t<decltype(Body::THREADS)>> {
+  static constexpr int value = Body::THREADS;
+};
+
+template <class Body>
+__global__ __launch_bounds__(ThreadsOf<Body>::value, Body::OCC) void k_single(KParams p) {
   const int b = blockIdx.x;
   const int w = (b & 7) * p.per_xcd + (b >> 3);
   if (w >= p.nblocks) return;
@@ -1601,7 +1615,7 @@ struct BatchOcc<Body, std::void_t<decltype(Body::OCC_BATCH)>> {
 };
 
 template <class Body>
-__global__ __launch_bounds__(256, BatchOcc<Body>::value) void k_batch(const KParams* __restrict__ beams,
+__global__ __launch_bounds__(ThreadsOf<Body>::value, BatchOcc<Body>::value) void k_batch(const KParams* __restrict__ beams,
                                                          const int32_t* __restrict__ first_item,
                                                          int32_t nbeams, int32_t total,
                                                          unsigned* __restrict__ counters) {
@@ -1659,6 +1673,7 @@ struct Impl {
   LinkedLayout table_pair;
   size_t in_size;
   bool needs_dword_rows;
+  int threads;  // per workgroup
 };
 
 template <class Body, class = void>
@@ -1747,12 +1762,30 @@ Impl make_impl() {
   m.table_pair = PairOf<Body>::layout;
   m.in_size = sizeof(Tin);
   m.needs_dword_rows = Body::table_epd != 0 || m.table_ralign != 0 || m.pairu8_idw != 0;
+  m.threads = ThreadsOf<Body>::value;
   return m;
 }
 
 bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
-  if (s.waves != 4) return false;
   const int v = s.variant, d = s.dms_per_wave, k = s.tsamp_per_lane;
+  // variant 7 also runs with 8 or 16 wavefronts per workgroup sharing one
+  // staged channel (fewer staged bytes per add)
+  if (in_t == DD_F32 && v == 7 && k == 12 && (s.waves == 8 || s.waves == 16)) {
+    if (s.waves == 8 && d == 6)
+      return *out = make_impl<BodyWinStage<6, 12, 4, 8, dd_v_f32_d6_k12_stage,
+                                           dd_v_f32_d6_k12_stagef>,
+                              float>(), true;
+    if (s.waves == 16 && d == 6)
+      return *out = make_impl<BodyWinStage<6, 12, 4, 16, dd_v_f32_d6_k12_stage,
+                                           dd_v_f32_d6_k12_stagef>,
+                              float>(), true;
+    if (s.waves == 8 && d == 8)
+      return *out = make_impl<BodyWinStage<8, 12, 3, 8, dd_v_f32_d8_k12_stage,
+                                           dd_v_f32_d8_k12_stagef>,
+                              float>(), true;
+    return false;
+  }
+  if (s.waves != 4) return false;
   if (v == 0 && d == 8 && k == 8) {
     if (in_t == DD_F32) return *out = make_impl<BodyLds<float, float, 8, 8>, float>(), true;
     if (in_t == DD_F16) return *out = make_impl<BodyLds<_Float16, float, 8, 8>, _Float16>(), true;
@@ -1798,15 +1831,15 @@ bool find_impl(const TileShape& s, dd_dtype in_t, Impl* out) {
   }
   if (in_t == DD_F32 && v == 7) {
     if (d == 8 && k == 12)
-      return *out = make_impl<BodyWinStage<8, 12, 3, dd_v_f32_d8_k12_stage,
+      return *out = make_impl<BodyWinStage<8, 12, 3, 4, dd_v_f32_d8_k12_stage,
                                            dd_v_f32_d8_k12_stagef>,
                               float>(), true;
     if (d == 6 && k == 12)
-      return *out = make_impl<BodyWinStage<6, 12, 4, dd_v_f32_d6_k12_stage,
+      return *out = make_impl<BodyWinStage<6, 12, 4, 4, dd_v_f32_d6_k12_stage,
                                            dd_v_f32_d6_k12_stagef>,
                               float>(), true;
     if (d == 4 && k == 12)
-      return *out = make_impl<BodyWinStage<4, 12, 5, dd_v_f32_d4_k12_stage,
+      return *out = make_impl<BodyWinStage<4, 12, 5, 4, dd_v_f32_d4_k12_stage,
                                            dd_v_f32_d4_k12_stagef>,
                               float>(), true;
   }
@@ -2035,7 +2068,8 @@ dd_status launch_dedisperse(const TileShape& s, dd_dtype in_t, const ExecArgs& a
   st = set_lds_limit(pl.impl.single, pl.lds);
   if (st != DD_OK) return st;
   void* args[] = {&pl.p};
-  DD_HIP(hipLaunchKernel(pl.impl.single, dim3(8 * pl.p.per_xcd), dim3(256), args, pl.lds, stream));
+  DD_HIP(hipLaunchKernel(pl.impl.single, dim3(8 * pl.p.per_xcd), dim3(pl.impl.threads), args,
+                         pl.lds, stream));
   return DD_OK;
 }
 
@@ -2076,12 +2110,13 @@ dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams
   out->total = static_cast<int32_t>(total);
   out->lds = lds;
   out->kernel = impl.batch;
+  out->threads = impl.threads;
   dd_status st = set_lds_limit(impl.batch, lds);
   if (st != DD_OK) return st;
   int dev = 0, ncu = 0, per_cu = 0;
   DD_HIP(hipGetDevice(&dev));
   DD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, impl.batch, 256, lds));
+  DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, impl.batch, impl.threads, lds));
   if (per_cu < 1) return set_error(DD_ERR_TOO_LARGE, "batch kernel does not fit a CU");
   out->grid = ((ncu * per_cu + 7) / 8) * 8;
   return DD_OK;
@@ -2099,7 +2134,7 @@ dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_
   int32_t total = b.total;
   unsigned* counters = d_counters;
   void* args[] = {&params, &first, &nbeams, &total, &counters};
-  DD_HIP(hipLaunchKernel(b.kernel, dim3(b.grid), dim3(256), args, b.lds, stream));
+  DD_HIP(hipLaunchKernel(b.kernel, dim3(b.grid), dim3(b.threads), args, b.lds, stream));
   return DD_OK;
 }
 

@@ -46,11 +46,11 @@ Key key_of(const dd_plan* plan, dd_dtype in_t, int64_t nsamp) {
   return Key{static_cast<int>(in_t), plan->nchans, plan->ndms, plan->max_shift, log2_ceil(nsamp)};
 }
 
-TileShape make(int v, int dw, int k, int cc) {
+TileShape make(int v, int dw, int k, int cc, int waves = 4) {
   TileShape s;
   s.variant = v;
   s.dms_per_wave = dw;
-  s.waves = 4;
+  s.waves = waves;
   s.tsamp_per_lane = k;
   s.chans_per_stage = cc;
   return s;
@@ -58,8 +58,9 @@ TileShape make(int v, int dw, int k, int cc) {
 
 std::vector<TileShape> candidates(dd_dtype in_t) {
   if (in_t == DD_F32)
-    return {make(7, 6, 12, 4), make(7, 8, 12, 8), make(6, 8, 12, 8), make(5, 8, 12, 8),
-            make(7, 4, 12, 4), make(5, 8, 20, 6), make(1, 8, 12, 8), make(0, 8, 8, 8)};
+    return {make(7, 6, 12, 8, 8), make(7, 6, 12, 12, 16), make(7, 6, 12, 4), make(7, 8, 12, 8),
+            make(6, 8, 12, 8),    make(5, 8, 12, 8),      make(7, 4, 12, 4), make(5, 8, 20, 6),
+            make(1, 8, 12, 8),    make(0, 8, 8, 8)};
   if (in_t == DD_U8)
     return {make(9, 8, 8, 4),  make(9, 16, 8, 4), make(9, 8, 16, 4), make(9, 8, 12, 4),
             make(3, 8, 16, 8), make(3, 8, 16, 4), make(3, 8, 8, 8),  make(0, 8, 8, 8)};
@@ -68,7 +69,7 @@ std::vector<TileShape> candidates(dd_dtype in_t) {
 }
 
 TileShape builtin_default(dd_dtype in_t) {
-  if (in_t == DD_F32) return make(7, 6, 12, 4);  // shared windows, threaded jumps, 4 waves/SIMD
+  if (in_t == DD_F32) return make(7, 6, 12, 8, 8);  // shared windows, 8-wave workgroups
   if (in_t == DD_U8) return make(9, 8, 8, 4);    // pair sums, 8 samples per lane
   return make(10, 8, 8, 4);                       // binary16 pair rows
 }

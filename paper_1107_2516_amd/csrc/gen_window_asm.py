@@ -506,9 +506,10 @@ def gen_stage(name, dw, k, occ, fast=False):
 
     In: acc, the first channel's entries as DW SGPR pairs (returned holding
     the entries of the channel after the stage), the first channel's LDS
-    address, the LDS stride between channels, the wavefront's table base and
-    the byte offset of the next channel's entries (advanced per channel), and
-    the channel count minus one.
+    address, the LDS stride between channels, the wavefront's table base, the
+    table's bytes per channel (the workgroup's DMs x 8), the byte offset of
+    the next channel's entries (advanced per channel), and the channel count
+    minus one.
 
     fast: each jump is s_add_u32 + s_setpc_b64 (the high word of the target
     is the table's, set once), which holds while no block offset carries out
@@ -535,7 +536,7 @@ def gen_stage(name, dw, k, occ, fast=False):
     sfx = "stagef" if fast else "stage"
     ret = "int" if fast else "void"
     out.append(f"__device__ __forceinline__ {ret} dd_{name}_{sfx}(float* acc, int2v* e, unsigned addr, "
-               f"unsigned lstride, const int32_t* tab, unsigned* toff, int cnt) {{")
+               f"unsigned lstride, const int32_t* tab, unsigned tstride, unsigned* toff, int cnt) {{")
     out.append("  unsigned va;")
     if fast:
         out.append("  int ok;")
@@ -632,7 +633,7 @@ def gen_stage(name, dw, k, occ, fast=False):
     if fast:
         outs.append('[ok] "=&s"(ok)')
     outs += [f'[e{i}] "+s"(e[{i}])' for i in range(dw)]
-    ins = ['[tp] "s"(tab)', '[ls] "s"(lstride)', f'[ts] "n"({4 * 2 * 4 * dw})']
+    ins = ['[tp] "s"(tab)', '[ls] "s"(lstride)', '[ts] "s"(tstride)']
     clob = [f'"v{wb + i}"' for i in range(3 * k)]
     clob += [f'"s{i}"' for i in range(SA, SA + 2 * dw)] + [f'"s{i}"' for i in range(SB, SB + nb)]
     clob += [f'"s{i}"' for i in (TPC, TPC + 1, TTG, TTG + 1)] + ['"scc"', '"memory"']

@@ -236,8 +236,11 @@ TILES_F32 = [
     dict(variant=7, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
     dict(variant=7, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=4),
     dict(variant=7, dms_per_wave=4, waves=4, tsamp_per_lane=12, chans_per_stage=4),
+    dict(variant=7, dms_per_wave=6, waves=8, tsamp_per_lane=12, chans_per_stage=8),
+    dict(variant=7, dms_per_wave=6, waves=16, tsamp_per_lane=12, chans_per_stage=12),
+    dict(variant=7, dms_per_wave=8, waves=8, tsamp_per_lane=12, chans_per_stage=6),
 ]
-TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}".format(**t) for t in TILES_F32]
+TILE_IDS = ["v{variant}_d{dms_per_wave}_k{tsamp_per_lane}_w{waves}".format(**t) for t in TILES_F32]
 
 
 @pytest.mark.parametrize("tile", TILES_F32, ids=TILE_IDS)
@@ -274,12 +277,13 @@ def test_threaded_jump_equals_indexed_window(order):
     xt = torch.from_numpy(x).cuda()
     ref = plan.execute_tiled(xt, dict(variant=1, dms_per_wave=8, waves=4, tsamp_per_lane=12,
                                       chans_per_stage=8))
-    for v, k, dw in [(6, 12, 8), (6, 20, 8), (6, 20, 4), (6, 12, 4), (7, 12, 8), (7, 12, 6),
-                      (7, 12, 4)]:
-        y = plan.execute_tiled(xt, dict(variant=v, dms_per_wave=dw, waves=4, tsamp_per_lane=k,
+    for v, k, dw, wv in [(6, 12, 8, 4), (6, 20, 8, 4), (6, 20, 4, 4), (6, 12, 4, 4),
+                         (7, 12, 8, 4), (7, 12, 6, 4), (7, 12, 4, 4), (7, 12, 6, 8),
+                         (7, 12, 6, 16), (7, 12, 8, 8)]:
+        y = plan.execute_tiled(xt, dict(variant=v, dms_per_wave=dw, waves=wv, tsamp_per_lane=k,
                                         chans_per_stage=8))
         torch.cuda.synchronize()
-        assert torch.equal(y, ref), (v, k, dw)
+        assert torch.equal(y, ref), (v, k, dw, wv)
     e, _ = scaled_error(ref.cpu().numpy(), x, tab)
     assert e <= FP_TOL, e
 
@@ -414,7 +418,7 @@ def test_autotune_then_execute(dtype):
 
 
 def test_one_plan_from_many_threads_and_streams():
-    """A fresh plan used by four host threads at once, each on its own stream
+    """A fresh plan used by five host threads at once, each on its own stream
     and with its own tile shape: the lazily built device tables are created
     once per layout under the plan's lock and every result matches the
     oracle."""
@@ -428,11 +432,12 @@ def test_one_plan_from_many_threads_and_streams():
     # variants 6 and 7 at 8 DMs per wave share the window shape but not the
     # block layout, so their jump tables must stay apart
     tiles = [dict(variant=7, dms_per_wave=6, waves=4, tsamp_per_lane=12, chans_per_stage=4),
+             dict(variant=7, dms_per_wave=6, waves=16, tsamp_per_lane=12, chans_per_stage=12),
              dict(variant=6, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
              dict(variant=7, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8),
              dict(variant=5, dms_per_wave=8, waves=4, tsamp_per_lane=12, chans_per_stage=8)]
-    outs, errs = [None] * 4, []
-    barrier = threading.Barrier(4)
+    outs, errs = [None] * len(tiles), []
+    barrier = threading.Barrier(len(tiles))
 
     def work(i):
         try:
@@ -445,7 +450,7 @@ def test_one_plan_from_many_threads_and_streams():
         except Exception as e:  # reported below
             errs.append(repr(e))
 
-    th = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(tiles))]
     for t in th:
         t.start()
     for t in th:
