@@ -213,7 +213,7 @@ dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, 
       if (static_cast<double>(items[i].nsamp) * items[i].plan->ndms * items[i].plan->nchans >
           static_cast<double>(items[big].nsamp) * items[big].plan->ndms * items[big].plan->nchans)
         big = static_cast<size_t>(i);
-    dd::TileShape s = dd::shape_for(items[big].plan, in_t, items[big].nsamp);
+    dd::TileShape s = dd::batch_shape(dd::shape_for(items[big].plan, in_t, items[big].nsamp), in_t);
     st = dd::configure(b.get(), s);
     if (st == DD_ERR_TOO_LARGE && s.variant != 0) st = dd::configure(b.get(), dd::default_shape(in_t, items[0].plan));
     if (st != DD_OK) return st;

@@ -42,6 +42,11 @@ struct TileShape {
     return std::tie(variant, dms_per_wave, waves, tsamp_per_lane, chans_per_stage) <
            std::tie(o.variant, o.dms_per_wave, o.waves, o.tsamp_per_lane, o.chans_per_stage);
   }
+  bool operator==(const TileShape& o) const {
+    return std::tie(variant, dms_per_wave, waves, tsamp_per_lane, chans_per_stage) ==
+           std::tie(o.variant, o.dms_per_wave, o.waves, o.tsamp_per_lane, o.chans_per_stage);
+  }
+  bool operator!=(const TileShape& o) const { return !(*this == o); }
 };
 
 // Device tables of one plan for one DM-tile height on one device.
@@ -276,6 +281,9 @@ struct BatchLaunch {
 };
 dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
                         BatchLaunch* out);
+// The shape a batch runs for a requested shape (shapes without a persistent
+// form map to one that has it).
+TileShape batch_shape(const TileShape& s, dd_dtype in_t);
 // Bytes of one beam's kernel parameters in a batch parameter array.
 size_t batch_param_size();
 // Zero the 8 work counters and launch the persistent kernel on `stream`.

@@ -2055,13 +2055,72 @@ TileShape default_shape(dd_dtype in_t, const dd_plan* plan) {
   return s;
 }
 
+// binary16 variant 11: the FP32 variant-7 kernel of the same shape on a
+// widened copy of the input
+TileShape widened_shape(const TileShape& s) {
+  TileShape f = s;
+  f.variant = 7;
+  return f;
+}
+
 bool shape_supported(const TileShape& s, dd_dtype in_t) {
   Impl m;
+  if (in_t == DD_F16 && s.variant == 11) return find_impl(widened_shape(s), DD_F32, &m);
   return find_impl(s, in_t, &m);
+}
+
+// Binary16 -> FP32 widening of nrows rows of n samples (exact: every binary16
+// value, subnormals included, is an FP32 value).  Memory-bound; a thread
+// converts four consecutive samples, with one 8-byte load and one 16-byte
+// store where both rows are aligned for it.
+__global__ __launch_bounds__(256) void k_widen_f16(const _Float16* __restrict__ in,
+                                                   int64_t in_stride, float* __restrict__ out,
+                                                   int64_t out_stride, int64_t n, int vec) {
+  const int64_t t = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (t >= n) return;
+  const _Float16* src = in + static_cast<int64_t>(blockIdx.y) * in_stride + t;
+  float* dst = out + static_cast<int64_t>(blockIdx.y) * out_stride + t;
+  if (vec && t + 4 <= n) {
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const h4 v = *reinterpret_cast<const h4*>(src);
+    *reinterpret_cast<f4*>(dst) = f4{static_cast<float>(v.x), static_cast<float>(v.y),
+                                     static_cast<float>(v.z), static_cast<float>(v.w)};
+    return;
+  }
+  for (int i = 0; i < 4 && t + i < n; i++) dst[i] = static_cast<float>(src[i]);
+}
+
+dd_status launch_widened(const TileShape& s, const ExecArgs& a, hipStream_t stream) {
+  // rows of the widened copy start on 256-byte boundaries
+  const int64_t pitch = (a.nsamp + 63) & ~int64_t(63);
+  const size_t bytes = static_cast<size_t>(a.nchans) * static_cast<size_t>(pitch) * sizeof(float);
+  void* tmp = nullptr;
+  DD_HIP(hipMallocAsync(&tmp, bytes, stream));
+  const bool vec = (reinterpret_cast<uintptr_t>(a.in) % 8 == 0) && (a.in_stride % 4 == 0);
+  const int64_t nthreads = (a.nsamp + 3) / 4;
+  hipLaunchKernelGGL(k_widen_f16, dim3(static_cast<unsigned>((nthreads + 255) / 256), a.nchans),
+                     dim3(256), 0, stream, static_cast<const _Float16*>(a.in), a.in_stride,
+                     static_cast<float*>(tmp), pitch, a.nsamp, vec ? 1 : 0);
+  hipError_t err = hipGetLastError();
+  dd_status st = DD_OK;
+  if (err != hipSuccess) {
+    st = hip_error(err, "launching the binary16 widening");
+  } else {
+    ExecArgs w = a;
+    w.in = tmp;
+    w.in_stride = pitch;
+    st = launch_dedisperse(widened_shape(s), DD_F32, w, stream);
+  }
+  // stream-ordered: the copy is released once the kernels queued before it finish
+  err = hipFreeAsync(tmp, stream);
+  if (st == DD_OK && err != hipSuccess) st = hip_error(err, "releasing the widened copy");
+  return st;
 }
 
 dd_status launch_dedisperse(const TileShape& s, dd_dtype in_t, const ExecArgs& a,
                             hipStream_t stream) {
+  if (in_t == DD_F16 && s.variant == 11) return launch_widened(s, a, stream);
   PreparedLaunch pl;
   dd_status st = prepare(s, in_t, a, &pl);
   if (st != DD_OK) return st;
@@ -2075,8 +2134,24 @@ dd_status launch_dedisperse(const TileShape& s, dd_dtype in_t, const ExecArgs& a
 
 // ---------------------------------------------------------------- batches
 
+TileShape batch_shape(const TileShape& s, dd_dtype in_t) {
+  if (in_t == DD_F16 && s.variant == 11) {
+    // no persistent form (the widened copies would be per beam): binary16
+    // pair rows instead
+    TileShape f = s;
+    f.variant = 10;
+    f.dms_per_wave = 8;
+    f.waves = 4;
+    f.tsamp_per_lane = 8;
+    f.chans_per_stage = 4;
+    return f;
+  }
+  return s;
+}
+
 dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
                         BatchLaunch* out) {
+  if (batch_shape(s, in_t) != s) return batch_prepare(batch_shape(s, in_t), in_t, beams, n, out);
   out->params.assign(static_cast<size_t>(n) * sizeof(KParams), 0);
   out->first_item.assign(static_cast<size_t>(n) + 1, 0);
   size_t lds = 0;

@@ -64,14 +64,14 @@ std::vector<TileShape> candidates(dd_dtype in_t) {
   if (in_t == DD_U8)
     return {make(9, 8, 8, 4),  make(9, 16, 8, 4), make(9, 8, 16, 4), make(9, 8, 12, 4),
             make(3, 8, 16, 8), make(3, 8, 16, 4), make(3, 8, 8, 8),  make(0, 8, 8, 8)};
-  return {make(10, 8, 8, 4), make(10, 8, 4, 4), make(3, 8, 8, 8), make(3, 8, 4, 8),
-          make(4, 8, 12, 8), make(0, 8, 8, 8)};
+  return {make(11, 6, 12, 8, 8), make(10, 8, 8, 4), make(10, 8, 4, 4), make(3, 8, 8, 8),
+          make(3, 8, 4, 8),     make(4, 8, 12, 8), make(0, 8, 8, 8)};
 }
 
 TileShape builtin_default(dd_dtype in_t) {
   if (in_t == DD_F32) return make(7, 6, 12, 8, 8);  // shared windows, 8-wave workgroups
   if (in_t == DD_U8) return make(9, 8, 8, 4);    // pair sums, 8 samples per lane
-  return make(10, 8, 8, 4);                       // binary16 pair rows
+  return make(11, 6, 12, 8, 8);  // widened to FP32, then the FP32 kernel
 }
 
 void load_file_locked() {
