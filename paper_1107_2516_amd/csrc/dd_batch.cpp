@@ -16,7 +16,8 @@
 struct dd_batch {
   dd_dtype in_t = DD_F32, out_t = DD_F32;
   std::vector<dd_batch_item> items;
-  dd::TileShape shape;
+  dd::TileShape shape;               // reported by dd_batch_info: forced, or the largest beam's
+  std::vector<dd::TileShape> shapes;  // per beam
   dd::BatchLaunch bl;
   int device = 0;
   int32_t* d_first = nullptr;  // prefix sums of work items (fixed between configures)
@@ -81,17 +82,18 @@ dd_status wait_idle(dd_batch* b) {
   return DD_OK;
 }
 
-// (Re)build the launch for shape s and upload its descriptor table to both
-// slots (after every replay in flight has completed).
-dd_status configure(dd_batch* b, const TileShape& s) {
+// (Re)build the launch for per-beam shapes and upload its descriptor table to
+// both slots (after every replay in flight has completed).
+dd_status configure(dd_batch* b, const std::vector<TileShape>& shapes, const TileShape& report) {
   BatchLaunch bl;
   std::vector<ExecArgs> a = exec_args(b->items);
-  dd_status st = batch_prepare(s, b->in_t, a.data(), static_cast<int>(a.size()), &bl);
+  dd_status st = batch_prepare(shapes.data(), b->in_t, a.data(), static_cast<int>(a.size()), &bl);
   if (st != DD_OK) return st;
   st = wait_idle(b);
   if (st != DD_OK) return st;
   if (!b->d_first) {
-    DD_HIP(hipMalloc(&b->d_first, bl.first_item.size() * sizeof(int32_t)));
+    // sized for the most kernel classes a batch can have
+    DD_HIP(hipMalloc(&b->d_first, 8 * (b->items.size() + kMaxBatchParts) * sizeof(int32_t)));
     for (auto& sl : b->slot) {
       DD_HIP(hipMalloc(&sl.d_params, bl.params.size()));
       DD_HIP(hipMalloc(&sl.d_counters, 64 * sizeof(unsigned)));
@@ -104,8 +106,23 @@ dd_status configure(dd_batch* b, const TileShape& s) {
                    hipMemcpyHostToDevice));
   drop_graphs(b);
   b->bl = std::move(bl);
-  b->shape = s;
+  b->shapes = shapes;
+  b->shape = report;
   return DD_OK;
+}
+
+dd_status configure(dd_batch* b, const TileShape& s) {
+  return configure(b, std::vector<TileShape>(b->items.size(), s), s);
+}
+
+// the beam with the most adds (its shape is the one reported)
+size_t largest_beam(const std::vector<dd_batch_item>& items) {
+  size_t big = 0;
+  for (size_t i = 1; i < items.size(); i++)
+    if (static_cast<double>(items[i].nsamp) * items[i].plan->ndms * items[i].plan->nchans >
+        static_cast<double>(items[big].nsamp) * items[big].plan->ndms * items[big].plan->nchans)
+      big = i;
+  return big;
 }
 
 dd_status capture(dd_batch* b, dd_batch::Slot& sl) {
@@ -126,12 +143,13 @@ dd_status capture(dd_batch* b, dd_batch::Slot& sl) {
 
 }  // namespace
 
-// Timing hook for the autotuner: enqueue the batch with shape s, uncaptured.
-dd_status batch_time_shape(dd_batch* b, const TileShape& s, hipStream_t stream, int reps,
-                           float* ms) {
+// Timing hook for the autotuner: enqueue the batch with per-beam shapes,
+// uncaptured.
+dd_status batch_time_shapes(dd_batch* b, const std::vector<TileShape>& shapes, hipStream_t stream,
+                            int reps, float* ms) {
   BatchLaunch bl;
   std::vector<ExecArgs> a = exec_args(b->items);
-  dd_status st = batch_prepare(s, b->in_t, a.data(), static_cast<int>(a.size()), &bl);
+  dd_status st = batch_prepare(shapes.data(), b->in_t, a.data(), static_cast<int>(a.size()), &bl);
   if (st != DD_OK) return st;
   // the timing runs share the current slot's counters: no replay may be in flight
   st = wait_idle(b);
@@ -170,6 +188,20 @@ dd_status batch_time_shape(dd_batch* b, const TileShape& s, hipStream_t stream, 
 
 dd_dtype batch_in_type(const dd_batch* b) { return b->in_t; }
 
+dd_status batch_time_shape(dd_batch* b, const TileShape& s, hipStream_t stream, int reps,
+                           float* ms) {
+  return batch_time_shapes(b, std::vector<TileShape>(b->items.size(), s), stream, reps, ms);
+}
+
+// The autotuner's per-beam pass: beam i's arguments, and the batch set to
+// per-beam shapes.
+size_t batch_size(const dd_batch* b) { return b->items.size(); }
+ExecArgs batch_beam_args(const dd_batch* b, size_t i) { return exec_args(b->items)[i]; }
+dd_status batch_set_shapes(dd_batch* b, const std::vector<TileShape>& shapes) {
+  std::lock_guard<std::mutex> lk(b->mu);
+  return configure(b, shapes, shapes[largest_beam(b->items)]);
+}
+
 dd_status batch_set_shape(dd_batch* b, const TileShape& s) {
   std::lock_guard<std::mutex> lk(b->mu);
   return configure(b, s);
@@ -206,16 +238,13 @@ dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, 
     b->out_t = out_t;
     b->items.assign(items, items + n);
     DD_HIP(hipGetDevice(&b->device));
-    // one tile shape for the whole batch: the tuned (or default) shape of the
-    // largest beam, else the LDS-streaming kernel when a beam does not suit it
-    size_t big = 0;
-    for (int32_t i = 1; i < n; i++)
-      if (static_cast<double>(items[i].nsamp) * items[i].plan->ndms * items[i].plan->nchans >
-          static_cast<double>(items[big].nsamp) * items[big].plan->ndms * items[big].plan->nchans)
-        big = static_cast<size_t>(i);
-    dd::TileShape s = dd::batch_shape(dd::shape_for(items[big].plan, in_t, items[big].nsamp), in_t);
-    st = dd::configure(b.get(), s);
-    if (st == DD_ERR_TOO_LARGE && s.variant != 0) st = dd::configure(b.get(), dd::default_shape(in_t, items[0].plan));
+    // each beam's tuned (or default) shape, beams grouped by kernel; the
+    // LDS-streaming kernel for all when a beam suits none of them
+    std::vector<dd::TileShape> shapes(static_cast<size_t>(n));
+    for (int32_t i = 0; i < n; i++)
+      shapes[i] = dd::batch_shape(dd::shape_for(items[i].plan, in_t, items[i].nsamp), in_t);
+    st = dd::configure(b.get(), shapes, shapes[dd::largest_beam(b->items)]);
+    if (st == DD_ERR_TOO_LARGE) st = dd::configure(b.get(), dd::default_shape(in_t, items[0].plan));
     if (st != DD_OK) return st;
     *out = b.release();
     return DD_OK;
@@ -246,12 +275,17 @@ dd_status dd_batch_update(dd_batch* b, const dd_batch_item* items, int32_t n) {
     b->items.assign(items, items + n);
     dd::BatchLaunch bl;
     std::vector<dd::ExecArgs> a = dd::exec_args(b->items);
-    st = dd::batch_prepare(b->shape, b->in_t, a.data(), n, &bl);
+    st = dd::batch_prepare(b->shapes.data(), b->in_t, a.data(), n, &bl);
     if (st != DD_OK) {
       b->items = keep;
       return st;
     }
-    if (bl.params.size() != b->bl.params.size() || bl.total != b->bl.total) {
+    bool same = bl.params.size() == b->bl.params.size() && bl.total == b->bl.total &&
+                bl.parts.size() == b->bl.parts.size();
+    for (size_t k = 0; same && k < bl.parts.size(); k++)
+      same = bl.parts[k].kernel == b->bl.parts[k].kernel &&
+             bl.parts[k].nbeams == b->bl.parts[k].nbeams && bl.parts[k].total == b->bl.parts[k].total;
+    if (!same) {
       b->items = keep;
       return dd::set_error(DD_ERR_STATE, "batch layout changed unexpectedly");
     }

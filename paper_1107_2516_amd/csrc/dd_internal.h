@@ -269,17 +269,34 @@ bool shape_supported(const TileShape& s, dd_dtype in_t);
 dd_status launch_dedisperse(const TileShape& shape, dd_dtype in_t, const ExecArgs& a,
                             hipStream_t stream);
 
-// A prepared persistent multi-beam launch (host side).
-struct BatchLaunch {
-  std::vector<unsigned char> params;  // per-beam kernel parameters, copied to the device
-  std::vector<int32_t> first_item;    // prefix sums of work items, nbeams + 1
-  int32_t total = 0;                  // work items
-  size_t lds = 0;                     // dynamic LDS per workgroup (max over beams)
+// One class of a batch: the beams that run the same kernel, as one
+// persistent launch.
+constexpr size_t kMaxBatchParts = 8;  // work counters: 8 per part, 64 in all
+struct BatchPart {
   const void* kernel = nullptr;
-  int grid = 0;                       // persistent grid: CUs x resident workgroups per CU
-  int threads = 256;                  // per workgroup
+  int grid = 0;           // persistent grid: CUs x resident workgroups per CU
+  int threads = 256;      // per workgroup
+  size_t lds = 0;         // dynamic LDS per workgroup (max over the part's beams)
+  int32_t nbeams = 0, total = 0;  // beams and work items of the part
+  size_t param_off = 0;   // bytes into params of the part's first beam
+  size_t first_off = 0;   // index into first_item of the part's table, 8 x (nbeams + 1)
+};
+// A prepared persistent multi-beam launch (host side): the parts run one
+// after the other on the stream.
+struct BatchLaunch {
+  std::vector<unsigned char> params;  // per-beam kernel parameters, grouped by part
+  std::vector<int32_t> first_item;    // per part, per eighth x: items of x before each beam
+  std::vector<BatchPart> parts;
+  int32_t total = 0;                  // work items of all parts
+  size_t lds = 0;                     // max over parts
+  const void* kernel = nullptr;       // the first part's (reported by dd_batch_info)
+  int grid = 0;                       // the first part's
+  int threads = 256;                  // the first part's
 };
 dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
+                        BatchLaunch* out);
+// The same with a shape per beam (shapes[i] for beam i).
+dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* beams, int n,
                         BatchLaunch* out);
 // The shape a batch runs for a requested shape (shapes without a persistent
 // form map to one that has it).

@@ -49,6 +49,7 @@
 //                  pattern, one v_add_u32 per two samples per pair and DM.
 // 10  BodyPairsF16: binary16 input; channel pairs packed per delay pattern,
 //                  one v_dot2_f32_f16 per sample per pair and DM.
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 
@@ -1598,11 +1599,16 @@ __global__ __launch_bounds__(ThreadsOf<Body>::value, Body::OCC) void k_single(KP
   Body::run(p, w % p.n_dtiles, w / p.n_dtiles);
 }
 
-// Persistent multi-beam kernel.  Items (beam, DM tile, time tile) are
-// numbered beam by beam; the item space is cut into 8 contiguous parts, part
-// x consumed first by the workgroups on XCD x (block b runs on XCD b mod 8)
-// through counter x, and afterwards by anyone (each workgroup tries the parts
-// in turn).  Every workgroup exits once all 8 parts are exhausted.
+// Persistent multi-beam kernel.  Items (beam, DM tile, time tile) of beam b
+// are numbered as in k_single (DM tile fastest); each beam's items are cut
+// into 8 contiguous eighths, and part x (consumed first by the workgroups on
+// XCD x, block b running on XCD b mod 8, through counter x) is the x-th
+// eighth of every beam, one beam after the other.  So every XCD does an
+// eighth of each beam, with the locality of a single launch, and the parts
+// carry equal work whatever the mix of beam shapes; a workgroup whose part
+// is exhausted takes items from the other parts in turn, and every workgroup
+// exits once all 8 are.  first8[x*(nbeams+1) + b] = items of part x that
+// belong to beams before b.
 // Occupancy of the persistent kernel: the body's own, except where the
 // work-fetch loop's extra live registers would make the body spill.
 template <class Body, class = void>
@@ -1616,37 +1622,41 @@ struct BatchOcc<Body, std::void_t<decltype(Body::OCC_BATCH)>> {
 
 template <class Body>
 __global__ __launch_bounds__(ThreadsOf<Body>::value, BatchOcc<Body>::value) void k_batch(const KParams* __restrict__ beams,
-                                                         const int32_t* __restrict__ first_item,
+                                                         const int32_t* __restrict__ first8,
                                                          int32_t nbeams, int32_t total,
                                                          unsigned* __restrict__ counters) {
+  (void)total;
   __shared__ int s_item, s_beam;
   const int xcd = blockIdx.x & 7;
   while (true) {
     if (threadIdx.x == 0) {
-      int item = -1;
+      int item = -1, beam = 0;
       for (int k = 0; k < 8 && item < 0; k++) {
         const int x = (xcd + k) & 7;
-        const int lo = static_cast<int>((static_cast<int64_t>(total) * x) / 8);
-        const int hi = static_cast<int>((static_cast<int64_t>(total) * (x + 1)) / 8);
-        if (lo >= hi) continue;
+        const int32_t* f = first8 + x * (nbeams + 1);
+        const int hi = f[nbeams];
+        if (hi <= 0) continue;
         const unsigned i = atomicAdd(&counters[x], 1u);
-        if (static_cast<int64_t>(lo) + i < hi) item = lo + static_cast<int>(i);
+        if (i < static_cast<unsigned>(hi)) {
+          const int j = static_cast<int>(i);
+          while (beam + 1 < nbeams && f[beam + 1] <= j) beam++;
+          // the item's index within its beam: the start of the beam's
+          // eighth x plus its rank within that eighth
+          item = static_cast<int>((static_cast<int64_t>(beams[beam].nblocks) * x) / 8) +
+                 (j - f[beam]);
+        }
       }
-      int beam = 0;
-      if (item >= 0)
-        while (beam + 1 < nbeams && first_item[beam + 1] <= item) beam++;
       s_item = item;
       s_beam = beam;
     }
     __syncthreads();
     // wave-uniform by construction; readfirstlane lets the compiler keep the
     // beam's parameters in SGPRs
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    const int local = __builtin_amdgcn_readfirstlane(s_item);
     const int beam = __builtin_amdgcn_readfirstlane(s_beam);
     __syncthreads();  // s_item / s_beam are rewritten on the next pass
-    if (item < 0) break;
+    if (local < 0) break;
     const KParams p = beams[beam];
-    const int local = item - first_item[beam];
     Body::run(p, local % p.n_dtiles, local / p.n_dtiles);
     __syncthreads();  // LDS is reused by the next item
   }
@@ -2151,49 +2161,89 @@ TileShape batch_shape(const TileShape& s, dd_dtype in_t) {
 
 dd_status batch_prepare(const TileShape& s, dd_dtype in_t, const ExecArgs* beams, int n,
                         BatchLaunch* out) {
-  if (batch_shape(s, in_t) != s) return batch_prepare(batch_shape(s, in_t), in_t, beams, n, out);
-  out->params.assign(static_cast<size_t>(n) * sizeof(KParams), 0);
-  out->first_item.assign(static_cast<size_t>(n) + 1, 0);
-  size_t lds = 0;
-  int64_t total = 0;
-  Impl impl{};
+  std::vector<TileShape> shapes(static_cast<size_t>(n), s);
+  return batch_prepare(shapes.data(), in_t, beams, n, out);
+}
+
+dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* beams, int n,
+                        BatchLaunch* out) {
+  // Beam i prepared with its shape (mapped to one with a persistent form);
+  // beams whose tables do not suit that shape's kernel get the kernel they
+  // fall back to.  Beams are grouped by kernel into classes, one persistent
+  // launch per class, launched one after the other.
+  std::vector<PreparedLaunch> pls(static_cast<size_t>(n));
+  std::vector<const void*> kinds;
+  std::vector<int> kind_of(static_cast<size_t>(n));
   for (int i = 0; i < n; i++) {
-    PreparedLaunch pl;
-    dd_status st = prepare(s, in_t, beams[i], &pl);
+    dd_status st = prepare(batch_shape(shapes[i], in_t), in_t, beams[i], &pls[i]);
     if (st != DD_OK) return st;
-    if (i > 0 && pl.impl.batch != impl.batch) {
-      // a pair-sum shape that some beams' tables do not fit: the whole batch
-      // takes the kernel those beams fall back to (one kernel per batch)
-      if (s.variant == 8 || s.variant == 9 || s.variant == 10) {
-        TileShape f = s;
-        f.variant = s.variant == 8 ? 7 : 3;
-        if (s.variant == 9) f.tsamp_per_lane = 16;
-        if (s.variant == 10) f.tsamp_per_lane = 8;
-        return batch_prepare(f, in_t, beams, n, out);
-      }
-      return set_error(DD_ERR_TOO_LARGE, "beams need different kernels for this shape");
+    auto it = std::find(kinds.begin(), kinds.end(), pls[i].impl.batch);
+    if (it == kinds.end()) {
+      if (kinds.size() == kMaxBatchParts)
+        return set_error(DD_ERR_TOO_LARGE, "beams need too many different kernels");
+      kinds.push_back(pls[i].impl.batch);
+      it = kinds.end() - 1;
     }
-    impl = pl.impl;
-    std::memcpy(out->params.data() + static_cast<size_t>(i) * sizeof(KParams), &pl.p,
-                sizeof(KParams));
-    out->first_item[i] = static_cast<int32_t>(total);
-    total += pl.p.nblocks;
-    if (total > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many work items");
-    lds = std::max(lds, pl.lds);
+    kind_of[i] = static_cast<int>(it - kinds.begin());
   }
-  out->first_item[n] = static_cast<int32_t>(total);
-  out->total = static_cast<int32_t>(total);
-  out->lds = lds;
-  out->kernel = impl.batch;
-  out->threads = impl.threads;
-  dd_status st = set_lds_limit(impl.batch, lds);
-  if (st != DD_OK) return st;
-  int dev = 0, ncu = 0, per_cu = 0;
+  out->params.assign(static_cast<size_t>(n) * sizeof(KParams), 0);
+  out->first_item.assign(8 * (static_cast<size_t>(n) + kinds.size()), 0);
+  out->parts.clear();
+  out->total = 0;
+  out->lds = 0;
+  int dev = 0, ncu = 0;
   DD_HIP(hipGetDevice(&dev));
   DD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, impl.batch, impl.threads, lds));
-  if (per_cu < 1) return set_error(DD_ERR_TOO_LARGE, "batch kernel does not fit a CU");
-  out->grid = ((ncu * per_cu + 7) / 8) * 8;
+  size_t pbeam = 0, pfirst = 0;
+  int64_t all = 0;
+  for (size_t k = 0; k < kinds.size(); k++) {
+    BatchPart part;
+    part.param_off = pbeam * sizeof(KParams);
+    part.first_off = pfirst;
+    std::vector<int64_t> nb_items;
+    for (int i = 0; i < n; i++) {
+      if (kind_of[i] != static_cast<int>(k)) continue;
+      std::memcpy(out->params.data() + pbeam * sizeof(KParams), &pls[i].p, sizeof(KParams));
+      nb_items.push_back(pls[i].p.nblocks);
+      part.lds = std::max(part.lds, pls[i].lds);
+      part.threads = pls[i].impl.threads;
+      pbeam++;
+    }
+    const int32_t nb = static_cast<int32_t>(nb_items.size());
+    // first8[x][b]: items of eighth x in the part's beams before b
+    int64_t total = 0;
+    for (int x = 0; x < 8; x++) {
+      int32_t* f = out->first_item.data() + pfirst + static_cast<size_t>(x) * (nb + 1);
+      int64_t acc = 0;
+      for (int32_t b = 0; b < nb; b++) {
+        f[b] = static_cast<int32_t>(acc);
+        acc += nb_items[b] * (x + 1) / 8 - nb_items[b] * x / 8;
+      }
+      f[nb] = static_cast<int32_t>(acc);
+      total += acc;
+      if (acc > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many work items");
+    }
+    pfirst += 8 * (static_cast<size_t>(nb) + 1);
+    part.kernel = kinds[k];
+    part.nbeams = nb;
+    part.total = static_cast<int32_t>(total);
+    dd_status st = set_lds_limit(part.kernel, part.lds);
+    if (st != DD_OK) return st;
+    int per_cu = 0;
+    DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, part.kernel, part.threads,
+                                                        part.lds));
+    if (per_cu < 1) return set_error(DD_ERR_TOO_LARGE, "batch kernel does not fit a CU");
+    part.grid = ((ncu * per_cu + 7) / 8) * 8;
+    out->parts.push_back(part);
+    out->lds = std::max(out->lds, part.lds);
+    all += total;
+  }
+  if (all > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many work items");
+  out->first_item.resize(pfirst);
+  out->total = static_cast<int32_t>(all);
+  out->kernel = out->parts[0].kernel;
+  out->grid = out->parts[0].grid;
+  out->threads = out->parts[0].threads;
   return DD_OK;
 }
 
@@ -2201,15 +2251,19 @@ size_t batch_param_size() { return sizeof(KParams); }
 
 dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
                         unsigned* d_counters, hipStream_t stream) {
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters, 8);
+  const int nparts = static_cast<int>(b.parts.size());
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters, 8 * nparts);
   DD_HIP(hipGetLastError());
-  const void* params = d_params;
-  const int32_t* first = d_first;
-  int32_t nbeams = static_cast<int32_t>(b.first_item.size()) - 1;
-  int32_t total = b.total;
-  unsigned* counters = d_counters;
-  void* args[] = {&params, &first, &nbeams, &total, &counters};
-  DD_HIP(hipLaunchKernel(b.kernel, dim3(b.grid), dim3(b.threads), args, b.lds, stream));
+  for (const BatchPart& part : b.parts) {
+    const void* params = static_cast<const unsigned char*>(d_params) + part.param_off;
+    const int32_t* first = d_first + part.first_off;
+    int32_t nbeams = part.nbeams;
+    int32_t total = part.total;
+    unsigned* counters = d_counters + 8 * (&part - b.parts.data());
+    void* args[] = {&params, &first, &nbeams, &total, &counters};
+    DD_HIP(hipLaunchKernel(part.kernel, dim3(part.grid), dim3(part.threads), args, part.lds,
+                           stream));
+  }
   return DD_OK;
 }
 

@@ -92,8 +92,9 @@ int stage2_items(const dd::Pass& ps) {
 
 // parameter array + prefix sums of one stage launch with n items
 size_t param_area(int n) {
+  // work tables: 8 x (nbeams + 1) per kernel class of the stage's batch
   return round256(static_cast<size_t>(n) * dd::batch_param_size()) +
-         round256(static_cast<size_t>(n + 1) * 4);
+         round256(8 * (static_cast<size_t>(n) + dd::kMaxBatchParts) * 4);
 }
 
 size_t params_workspace(const dd_subband_plan* sp) {

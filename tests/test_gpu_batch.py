@@ -211,3 +211,47 @@ def test_batch_set_tile_every_u8_shape():
     for (tab, x), o in zip(beams, outs):
         _check(o.cpu().numpy(), x, tab, "u8")
 
+
+
+def test_batch_mixed_kernel_classes():
+    """A batch whose beams need different kernels for one shape: the 8-bit
+    pair-row shape suits the dispersion-law beams but not a random shift
+    table (too many delay patterns per pair), so the batch runs as two
+    persistent launches, one per kernel class.  Every beam equals the
+    oracle, also after a graph replay and an update to new buffers."""
+    g = np.random.default_rng(41)
+    beams = []
+    for nchans, ndms, extra in [(1024, 300, 2501), (512, 200, 1702)]:
+        b = synth.Band(nchans, 1510.0, 296.0 / nchans, 64e-6)
+        tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, synth.dm_grid(ndms, 0.5))
+        beams.append(tab)
+    beams.insert(1, np.sort(rand_table(g, 75, 70, 400), axis=0))
+    plans = [dd.Plan.from_delays(t) for t in beams]
+
+    def inputs(seed):
+        gg = np.random.default_rng(seed)
+        hs, ds = [], []
+        for t in beams:
+            x = np.clip(np.rint(128 + 16 * gg.standard_normal((t.shape[1], int(t.max()) + 3000))),
+                        0, 255).astype(np.uint8)
+            buf = torch.zeros((x.shape[0], (x.shape[1] + 63) // 64 * 64), dtype=torch.uint8,
+                              device="cuda")
+            buf[:, :x.shape[1]].copy_(torch.from_numpy(x))
+            hs.append(x)
+            ds.append(buf[:, :x.shape[1]])
+        return hs, ds
+
+    hs, ds = inputs(1)
+    bt = dd.Batch([(p, x, None) for p, x in zip(plans, ds)])
+    bt.set_tile(dict(variant=9, dms_per_wave=8, waves=4, tsamp_per_lane=8, chans_per_stage=4))
+    for _ in range(2):  # capture, then replay
+        outs = bt.launch()
+        torch.cuda.synchronize()
+        for t, x, o in zip(beams, hs, outs):
+            assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t))
+    hs2, ds2 = inputs(2)
+    bt.update(inputs=ds2)
+    outs = bt.launch()
+    torch.cuda.synchronize()
+    for t, x, o in zip(beams, hs2, outs):
+        assert np.array_equal(o.cpu().numpy().astype(np.int64), oracle.dedisperse(x, t))

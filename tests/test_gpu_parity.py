@@ -417,6 +417,21 @@ def test_autotune_then_execute(dtype):
     _check(plan, x, tab, dtype)
 
 
+@pytest.mark.parametrize("dtype", ["u8", "f16"])
+def test_autotune_odd_length_times_the_fast_kernels(dtype):
+    """The autotuner's scratch rows are pitched like a caller's, so for an odd
+    row length the 8-bit and binary16 kernels that need dword-aligned rows
+    still run and one of them (not the LDS-streaming fallback, several times
+    slower) is remembered."""
+    b = synth.Band(1024, 1510.0, 296.0 / 1024, 64e-6)
+    plan = dd.Plan(b.nchans, b.f_top, b.df, b.t_samp, synth.dm_grid(512, 0.5))
+    nsamp = plan.max_shift + 20001  # odd
+    tdt = {"f16": torch.float16, "u8": torch.uint8}[dtype]
+    tile, ms = plan.autotune(tdt, nsamp)
+    assert ms > 0
+    assert tile["variant"] != 0, tile
+
+
 def test_one_plan_from_many_threads_and_streams():
     """A fresh plan used by five host threads at once, each on its own stream
     and with its own tile shape: the lazily built device tables are created
