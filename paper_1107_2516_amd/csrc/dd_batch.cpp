@@ -125,6 +125,9 @@ size_t largest_beam(const std::vector<dd_batch_item>& items) {
   return big;
 }
 
+// Record one replay: the counter reset and the parts one after the other
+// (parts recorded as parallel branches ran concurrently and slower: two
+// persistent kernels of different shapes share the CUs badly).
 dd_status capture(dd_batch* b, dd_batch::Slot& sl) {
   if (!b->cap_stream) DD_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   DD_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -303,9 +303,14 @@ dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* 
 TileShape batch_shape(const TileShape& s, dd_dtype in_t);
 // Bytes of one beam's kernel parameters in a batch parameter array.
 size_t batch_param_size();
-// Zero the 8 work counters and launch the persistent kernel on `stream`.
+// Zero the work counters (8 per part) and launch the parts' persistent
+// kernels on `stream`, one after the other.
 dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
                         unsigned* d_counters, hipStream_t stream);
+// The same in pieces: the counter reset (before any part), and part k.
+dd_status batch_zero_counters(const BatchLaunch& b, unsigned* d_counters, hipStream_t stream);
+dd_status batch_enqueue_part(const BatchLaunch& b, size_t k, const void* d_params,
+                             const int32_t* d_first, unsigned* d_counters, hipStream_t stream);
 
 // Tile-shape selection (dd_tune.cpp).
 TileShape shape_for(const dd_plan* plan, dd_dtype in_t, int64_t nsamp);

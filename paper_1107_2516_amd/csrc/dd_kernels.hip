@@ -2249,22 +2249,33 @@ dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* 
 
 size_t batch_param_size() { return sizeof(KParams); }
 
+dd_status batch_zero_counters(const BatchLaunch& b, unsigned* d_counters, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters,
+                     8 * static_cast<int>(b.parts.size()));
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+dd_status batch_enqueue_part(const BatchLaunch& b, size_t k, const void* d_params,
+                             const int32_t* d_first, unsigned* d_counters, hipStream_t stream) {
+  const BatchPart& part = b.parts[k];
+  const void* params = static_cast<const unsigned char*>(d_params) + part.param_off;
+  const int32_t* first = d_first + part.first_off;
+  int32_t nbeams = part.nbeams;
+  int32_t total = part.total;
+  unsigned* counters = d_counters + 8 * k;
+  void* args[] = {&params, &first, &nbeams, &total, &counters};
+  DD_HIP(hipLaunchKernel(part.kernel, dim3(part.grid), dim3(part.threads), args, part.lds,
+                         stream));
+  return DD_OK;
+}
+
 dd_status batch_enqueue(const BatchLaunch& b, const void* d_params, const int32_t* d_first,
                         unsigned* d_counters, hipStream_t stream) {
-  const int nparts = static_cast<int>(b.parts.size());
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters, 8 * nparts);
-  DD_HIP(hipGetLastError());
-  for (const BatchPart& part : b.parts) {
-    const void* params = static_cast<const unsigned char*>(d_params) + part.param_off;
-    const int32_t* first = d_first + part.first_off;
-    int32_t nbeams = part.nbeams;
-    int32_t total = part.total;
-    unsigned* counters = d_counters + 8 * (&part - b.parts.data());
-    void* args[] = {&params, &first, &nbeams, &total, &counters};
-    DD_HIP(hipLaunchKernel(part.kernel, dim3(part.grid), dim3(part.threads), args, part.lds,
-                           stream));
-  }
-  return DD_OK;
+  dd_status st = batch_zero_counters(b, d_counters, stream);
+  for (size_t k = 0; st == DD_OK && k < b.parts.size(); k++)
+    st = batch_enqueue_part(b, k, d_params, d_first, d_counters, stream);
+  return st;
 }
 
 }  // namespace dd
