@@ -123,11 +123,15 @@ dd_status dd_plan_destroy(dd_plan* plan);
  * DD_ERR_HIP (launch failure).
  * Accuracy.  8-bit input gives exact int32 sums.  Float input (f32, or f16
  * converted exactly to FP32) is summed in FP32 one channel at a time in
- * channel order 0..nchans-1, so every kernel variant, batch and serving path
- * gives bit-identical FP32 results for one input, and the error against the
- * exact sum obeys the recursive-summation bound
+ * channel order 0..nchans-1 by the default shapes and every variant up to 7
+ * and 11, so they, batches and serving give bit-identical FP32 results for one
+ * input, and the error against the exact sum obeys the recursive-summation
+ * bound
  *     |y - y*| <= (nchans - 1) 2^-24 sum_c |x_c|      (first order),
  * i.e. a scaled error of at most 6.1e-5 at 1024 channels and 1.2e-4 at 2048.
+ * Variants 8 (FP32) and 10 (binary16) first add channels in pairs and then
+ * the pair sums in order: a different rounding, within (nchans/2) 2^-24
+ * sum_c |x_c|.
  * Realised errors are far smaller: ~2e-7 on zero-mean noise and ~2e-6 on
  * noise with a large positive offset; the worst inputs found, constant
  * positive values whose every partial sum rounds the same way, reach
@@ -154,10 +158,13 @@ typedef struct dd_batch_item {
 
 /*
  * Describe `n` beams that share (in_t, out_t) and are processed together by
- * one persistent kernel: every (beam, DM tile, time tile) work item is pulled
- * from a device queue by a fixed grid sized to the GPU.  Tile shapes come from
- * the autotune cache (dd_autotune) or the built-in defaults.  The launch is
- * recorded into a HIP graph on first use and replayed afterwards.
+ * persistent kernels: every (beam, DM tile, time tile) work item is pulled
+ * from a device queue by a fixed grid sized to the GPU, each XCD taking an
+ * eighth of every beam first.  Each beam's tile shape comes from the
+ * autotune cache (dd_autotune) or the built-in defaults; beams whose shapes
+ * run different kernels form classes, one persistent kernel per class, run
+ * one after the other (at most 8 classes, else DD_ERR_TOO_LARGE).  The launch
+ * is recorded into a HIP graph on first use and replayed afterwards.
  */
 dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, dd_dtype out_t,
                           dd_batch** out);
@@ -177,13 +184,15 @@ dd_status dd_batch_update(dd_batch* batch, const dd_batch_item* items, int32_t n
 dd_status dd_batch_launch(dd_batch* batch, void* stream);
 
 /* Use tile shape *cfg for every beam of the batch (its graph is re-recorded
- * on the next launch).  DD_ERR_NOT_IMPLEMENTED for a shape no kernel has,
- * DD_ERR_TOO_LARGE when some beam does not fit it (the batch keeps its
- * previous shape then). */
+ * on the next launch); a beam whose tables do not suit the shape's kernel
+ * runs the kernel that shape falls back to, in its own class.
+ * DD_ERR_NOT_IMPLEMENTED for a shape no kernel has, DD_ERR_TOO_LARGE when
+ * some beam does not fit it (the batch keeps its previous shapes then). */
 dd_status dd_batch_set_tile(dd_batch* batch, const dd_tile_config* cfg);
 
-/* Work items (beam, DM tile, time tile), persistent grid size and the tile
- * shape of a batch; any output pointer may be NULL. */
+/* Work items (beam, DM tile, time tile), persistent grid size (of the first
+ * class) and the tile shape of a batch (the forced one, or the largest
+ * beam's); any output pointer may be NULL. */
 dd_status dd_batch_info(const dd_batch* batch, int32_t* work_items, int32_t* grid,
                         dd_tile_config* cfg);
 
@@ -197,9 +206,11 @@ dd_status dd_batch_destroy(dd_batch* batch);
 
 /*
  * Time the candidate tile shapes for (plan, in_t, nsamp) on `stream` using
- * scratch buffers it allocates and frees, keep the fastest in the process-wide
- * cache (and in the file named by DD_TUNE_CACHE, if set), and return it.
- * Blocks until the timing is done.  best_ms may be NULL.
+ * scratch buffers it allocates and frees (rows pitched to 64 samples), keep
+ * the fastest in the process-wide cache (and in the file named by
+ * DD_TUNE_CACHE, if set: one line per entry, led by the GPU architecture
+ * name, so lines written on another GPU model are not applied), and return
+ * it.  Blocks until the timing is done.  best_ms may be NULL.
  */
 dd_status dd_autotune(const dd_plan* plan, dd_dtype in_t, int64_t nsamp, void* stream,
                       dd_tile_config* best, float* best_ms);
@@ -217,8 +228,11 @@ dd_status dd_execute_tiled(const dd_plan* plan, const void* d_in, dd_dtype in_t,
 
 /*
  * Time the candidate tile shapes on the batch itself (its output buffers are
- * overwritten), keep the fastest for the batch and re-record its graph on
- * the next launch.  Blocks until the timing is done.  best_ms may be NULL.
+ * overwritten): each shape for every beam, and each beam on its own with
+ * every shape (the per-beam winners are remembered in the shape cache and
+ * timed together); keep the faster configuration and re-record the graph on
+ * the next launch.  *best is the chosen uniform shape, or the largest beam's.
+ * Blocks until the timing is done.  best_ms may be NULL.
  */
 dd_status dd_batch_autotune(dd_batch* batch, void* stream, dd_tile_config* best, float* best_ms);
 
@@ -464,8 +478,10 @@ dd_status dd_corner_turn(const void* d_in, dd_dtype type, int64_t nsamp, int32_t
  * entries[g*2*dw + j] (block byte offset) and entries[g*2*dw + dw + j]
  * (window start, samples, a multiple of 4) for the block table of window
  * `wmax` registers and k adds per block.  dw in {4, 8}, k a multiple of 4,
- * wmax a multiple of 4 and >= k + 4.  DD_ERR_INVALID_ARG for other shapes or
- * a negative shift.
+ * wmax a multiple of 4 and >= k + 4.  wmax = 0 selects instead the layout of
+ * the FP32 default kernel (tile variant 7): a window of 4k samples shared
+ * between neighbouring lanes, dw in 2..8, k a multiple of 4 up to 64.
+ * DD_ERR_INVALID_ARG for other shapes or a negative shift.
  *
  * dd_jump_table_check: DD_OK when every entry names a block of its own DM's
  * slot (the first DM's a window load), every window start is a multiple of 4

@@ -171,9 +171,15 @@ const char* dd_version(void) { return "0.1.0"; }
 
 extern "C" {
 
+// wmax == 0: the shared-window layout of FP32 variant 7 (window 4k)
 static bool jump_shape_ok(int32_t dw, int32_t k, int32_t wmax) {
+  if (wmax == 0) return dw >= 2 && dw <= 8 && k >= 4 && k % 4 == 0 && k <= 64;
   return (dw == 4 || dw == 8) && k >= 4 && k % 4 == 0 && wmax % 4 == 0 && wmax >= k + 4 &&
          wmax <= 256;
+}
+
+static dd::JumpLayout jump_shape(int32_t dw, int32_t k, int32_t wmax) {
+  return wmax == 0 ? dd::shared_jump_layout(dw, k) : dd::jump_layout(dw, k, wmax);
 }
 
 dd_status dd_jump_table_build(const int32_t* rel, int64_t ngroups, int32_t dw, int32_t k,
@@ -181,7 +187,7 @@ dd_status dd_jump_table_build(const int32_t* rel, int64_t ngroups, int32_t dw, i
   DD_GUARD_BEGIN
   if (!rel || !entries || ngroups < 0) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
   if (!jump_shape_ok(dw, k, wmax)) return dd::set_error(DD_ERR_INVALID_ARG, "bad block-table shape");
-  return dd::build_jump_entries(rel, ngroups, dd::jump_layout(dw, k, wmax), entries);
+  return dd::build_jump_entries(rel, ngroups, jump_shape(dw, k, wmax), entries);
   DD_GUARD_END
 }
 
@@ -190,7 +196,7 @@ dd_status dd_jump_table_check(const int32_t* entries, const int32_t* rel, int64_
   DD_GUARD_BEGIN
   if (!rel || !entries || ngroups < 0) return dd::set_error(DD_ERR_INVALID_ARG, "NULL argument");
   if (!jump_shape_ok(dw, k, wmax)) return dd::set_error(DD_ERR_INVALID_ARG, "bad block-table shape");
-  return dd::check_jump_entries(entries, rel, ngroups, dd::jump_layout(dw, k, wmax));
+  return dd::check_jump_entries(entries, rel, ngroups, jump_shape(dw, k, wmax));
   DD_GUARD_END
 }
 

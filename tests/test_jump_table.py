@@ -18,14 +18,26 @@ import oracle
 import paper_1107_2516_amd as dd
 import synth
 
-SHAPES = [(8, 12, 48), (8, 20, 56), (4, 20, 56)]
+# (dw, k, wmax); wmax 0 is the shared-window layout of the FP32 default
+# kernel (variant 7, window 4k)
+SHAPES = [(8, 12, 48), (8, 20, 56), (4, 20, 56), (6, 12, 0), (8, 12, 0), (4, 12, 0)]
 
 
 def layout(dw, k, wmax):
-    """Block-table layout as documented in the header: dw*np plain blocks of
-    4k+12 bytes, then dw*4 reload blocks of 2*wmax+4k+32 bytes."""
+    """Block-table layout: dw*np plain blocks, then dw*4 reload blocks.
+    Private windows (variant 6): np = wmax-k+1 offsets, plain blocks of
+    4k+12 bytes, reload blocks of 2*wmax+4k+32 bytes.  Shared windows
+    (variant 7, wmax 0): np = 3k+1 offsets in a window of 4k, plain blocks of
+    8k+12 bytes (up to k DPP adds of 8 bytes), reload blocks of 10k+32 bytes
+    (3k/4 window reads of 8 bytes, k adds of 4)."""
+    if wmax == 0:
+        return 3 * k + 1, 8 * k + 12, 10 * k + 32
     np_ = wmax - k + 1
     return np_, 4 * k + 12, 2 * wmax + 4 * k + 32
+
+
+def window(k, wmax):
+    return 4 * k if wmax == 0 else wmax
 
 
 def build(rel, dw, k, wmax):
@@ -67,10 +79,10 @@ def decode(ent, dw, k, wmax):
 
 @pytest.mark.parametrize("dw,k,wmax", SHAPES)
 def test_random_shifts_build_check_and_decode(dw, k, wmax):
-    g = np.random.default_rng(dw * 1000 + k)
+    g = np.random.default_rng(dw * 1000 + k + wmax)
     ng = 3000
     # sorted groups with spreads from 0 to far beyond the window, and unsorted groups
-    spread = g.integers(0, 4 * wmax, ng)
+    spread = g.integers(0, 4 * window(k, wmax), ng)
     rel = np.sort(g.integers(0, 1 << 20, (ng, dw)) % (spread[:, None] + 1), axis=1)
     rel[: ng // 3] = g.integers(0, 300, (ng // 3, dw))
     rel += g.integers(0, 3000, (ng, 1))
@@ -82,16 +94,19 @@ def test_random_shifts_build_check_and_decode(dw, k, wmax):
 
 def test_scale_workload_tiles():
     """Every (tile, channel, wavefront) of the 1024-channel, 2048-DM workload
-    with 32-DM tiles: the table passes the checker and decodes to the tile's
-    shifts; most DMs reuse their wavefront's window."""
+    with the kernels' DM tiles: the table passes the checker and decodes to
+    the tile's shifts; most DMs reuse their wavefront's window."""
     w = synth.scale()
     b = w.band
     tab = oracle.delay_table(b.nchans, b.f_top, b.df, b.t_samp, w.dms)  # [ndms][nchans]
-    td = 32
-    t = tab.reshape(-1, td, b.nchans)  # increasing DMs: tile order is the DM order
-    rel = t - t.min(axis=1, keepdims=True)  # [tile][j][c]
-    rel = np.ascontiguousarray(rel.transpose(0, 2, 1))  # [tile][c][j]
     for dw, k, wmax in SHAPES:
+        # 4-wave tiles for the private windows, the default 8-wave tiles for
+        # the shared ones (48 DMs: the first 2016 of the 2048)
+        td = 4 * dw if wmax else 8 * dw
+        n = tab.shape[0] // td * td
+        t = tab[:n].reshape(-1, td, b.nchans)  # increasing DMs: tile order is the DM order
+        rel = t - t.min(axis=1, keepdims=True)  # [tile][j][c]
+        rel = np.ascontiguousarray(rel.transpose(0, 2, 1))  # [tile][c][j]
         r = rel.reshape(-1, dw)
         st, ent = build(r, dw, k, wmax)
         assert st == dd.DD_OK
@@ -100,7 +115,7 @@ def test_scale_workload_tiles():
         offs = ent.reshape(-1, 2 * dw)[:, :dw]
         reload = (offs >= dw * np_ * pbs).mean()
         assert reload < 0.5, reload  # DM 0 always reloads: at least 1/dw
-        if dw == 8 and k == 12:
+        if k == 12:
             assert np.array_equal(decode(ent[: 2 * dw * 20000], dw, k, wmax), r[:20000].reshape(-1))
 
 
@@ -110,7 +125,7 @@ def test_planted_mistakes_are_rejected(dw, k, wmax):
     plain_end = dw * np_ * pbs
     table_end = plain_end + dw * 4 * rbs
     g = np.random.default_rng(5)
-    rel = np.sort(g.integers(0, wmax // 2, (200, dw)), axis=1) + 8
+    rel = np.sort(g.integers(0, window(k, wmax) // 2, (200, dw)), axis=1) + 8
     st, ent = build(rel, dw, k, wmax)
     assert st == dd.DD_OK and check(ent, rel, dw, k, wmax) == dd.DD_OK
     e = ent.reshape(-1, 2 * dw)
