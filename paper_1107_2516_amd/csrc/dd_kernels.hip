@@ -721,7 +721,19 @@ struct BodyPairsU8 {
             const_cast<unsigned char*>(in + static_cast<int64_t>(c) * row_bytes), 0,
             full_dwords * 4, 0x00020000);
         uint32_t* dst = raw + i * slotr;
-        for (int e = 0; e < slotr; e += 64)
+        int e = 0;
+        if (gd >= 0) {
+          // 16-byte copies (each lane's four dwords land contiguously) for
+          // whole groups of 256 dwords; a row starting before dword 0 (the
+          // margin dword at the very start) keeps the one-dword copies
+#pragma unroll 1
+          for (; e + 256 <= slotr; e += 256)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (lds_void_t*)(dst + e), 16, static_cast<unsigned>(gd + e + 4 * lane) * 4u, 0,
+                0, 0);
+        }
+#pragma unroll 1
+        for (; e < slotr; e += 64)
           __builtin_amdgcn_raw_ptr_buffer_load_lds(
               rs, (lds_void_t*)(dst + e), 4, static_cast<unsigned>(gd + e + lane) * 4u, 0, 0, 0);
       }
@@ -756,7 +768,10 @@ struct BodyPairsU8 {
       }
     };
     // pattern rows of stage s: wave w builds rows w, w+4, ... (a row's pair
-    // and shift are wave-uniform scalar loads)
+    // and shift are wave-uniform scalar loads).  units is a multiple of 64
+    // (geometry), so every lane runs every pass of the unit loop and its
+    // count stays in scalar registers; the single-channel case (an odd
+    // channel count's last pair) has a loop of its own.
     auto build = [&](int s) {
       const int32_t* rec = p.aux + (static_cast<int64_t>(dtile) * nstage + s) * rw;
       const int nrows = cload1(rec);
@@ -770,22 +785,33 @@ struct BodyPairsU8 {
         const uint32_t* yr = raw + (2 * pl + 1) * slotr;
         uint32_t* r0 = pr + (2 * row) * slotp;
         uint32_t* r1 = r0 + slotp;
-        for (int u = lane; u < units; u += 64) {
-          const uint32_t xa = xr[u], xb = xr[u + 1];
-          uint32_t ya = 0, yb = 0;
-          if (two) {
-            // dword of x_c+1 at byte 4u + d, kept inside the row (only units
-            // that no DM reads are ever clamped)
-            const int i0 = min(max(u + (d >> 2) + 1, 0), slotr - 3);
-            const uint32_t y0 = yr[i0], y1 = yr[i0 + 1], y2 = yr[i0 + 2];
-            ya = __builtin_amdgcn_alignbyte(y1, y0, static_cast<unsigned>(d & 3));
-            yb = __builtin_amdgcn_alignbyte(y2, y1, static_cast<unsigned>(d & 3));
-          }
+        auto emit = [&](int u, uint32_t xa, uint32_t xb, uint32_t ya, uint32_t yb) {
           auto pick = [&](unsigned sel) {
             return __builtin_amdgcn_perm(xb, xa, sel) + __builtin_amdgcn_perm(yb, ya, sel);
           };
           *reinterpret_cast<uint2*>(r0 + 2 * u) = make_uint2(pick(0x0c010c00u), pick(0x0c030c02u));
           *reinterpret_cast<uint2*>(r1 + 2 * u) = make_uint2(pick(0x0c020c01u), pick(0x0c040c03u));
+        };
+        if (two) {
+          const unsigned sh = static_cast<unsigned>(d & 3);
+          const int dq = (d >> 2) + 1;
+#pragma unroll 1
+          for (int u0 = 0; u0 < units; u0 += 64) {
+            const int u = u0 + lane;
+            const uint32_t xa = xr[u], xb = xr[u + 1];
+            // dword of x_c+1 at byte 4u + d, kept inside the row (only units
+            // that no DM reads are ever clamped)
+            const int i0 = min(max(u + dq, 0), slotr - 3);
+            const uint32_t y0 = yr[i0], y1 = yr[i0 + 1], y2 = yr[i0 + 2];
+            emit(u, xa, xb, __builtin_amdgcn_alignbyte(y1, y0, sh),
+                 __builtin_amdgcn_alignbyte(y2, y1, sh));
+          }
+        } else {
+#pragma unroll 1
+          for (int u0 = 0; u0 < units; u0 += 64) {
+            const int u = u0 + lane;
+            emit(u, xr[u], xr[u + 1], 0u, 0u);
+          }
         }
       }
     };
@@ -848,8 +874,10 @@ struct BodyPairsU8 {
     if (since_flush || first) flush();
   }
   static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
-    // a DM's first dword is (R >> 1) with R <= span_max + 3; it reads 64*IDW dwords
-    const int sp = (64 * IDW + (span_max + 3) / 2 + 1 + 63) & ~63;
+    // a DM's first dword is (R >> 1) with R <= span_max + 3; it reads 64*IDW
+    // dwords.  A multiple of 128, so the build's unit loop (slot/2 units of
+    // two dwords) has whole passes of 64 lanes.
+    const int sp = (64 * IDW + (span_max + 3) / 2 + 1 + 127) & ~127;
     const int budget = 160 * 1024 / OCC / 4;  // dwords
     int c = max(2, cc_req & ~1);
     // at least two pattern rows per pair of the stage; whether a plan's
