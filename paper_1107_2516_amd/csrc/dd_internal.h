@@ -64,6 +64,7 @@ struct TileTables {
   int32_t* d_base = nullptr;
   int32_t* d_rel = nullptr;
   int32_t* d_rows = nullptr;
+  int32_t* d_span = nullptr;  // [tile][c]: largest rel of the tile at channel c
 };
 
 struct DeviceTables {

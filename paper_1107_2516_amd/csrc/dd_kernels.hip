@@ -317,23 +317,23 @@ struct BodyWin {
                 "shared windows: threaded-jump step, window 4K, two supplying lanes");
 };
 
-// ------------------------------------------------------- variant 7 (stages)
+// ---------------------------------------------------------------- variant 7
 //
-// The shared-window threaded-jump step with the channel loop inside the
-// assembly: a call runs every channel of one stage.  On gfx950 a CU issues
-// about one scalar instruction per clock against two vector adds, so the
-// scalar work around each channel (loop control, table addressing, entry
-// hand-over, staging address arithmetic) set the pace of the per-channel
-// step; here it is cut to the jumps, DW 64-bit entry moves and three loop
-// instructions per channel.  Staging copies 16 bytes per lane per DMA
-// instruction (buffer_load_dwordx4 ... lds writes each lane's 16 bytes
-// contiguously, and its range check is per dword, so the last partial vector
-// of a row keeps its in-range samples and zero-fills the rest), four
-// instructions per M0 value through immediate offsets; slots are whole
-// multiples of 256 samples so that no copy spills into the next channel's.
-// Each wave's channel offset for the next stage is read a stage ahead.  The
-// blocks, table layout and entries are variant 7's, so the arithmetic and its
-// order are the same and so are the results, bit for bit.
+// The shared-window threaded-jump step (gen_stage in gen_window_asm.py) with
+// the channel loop inside the assembly: a call runs every channel of one
+// stage.  On gfx950 a CU issues about one scalar instruction per clock against
+// two vector adds, so the scalar work around each channel (loop control,
+// table addressing, entry hand-over, staging address arithmetic) is cut to
+// the jumps, DW 64-bit entry moves and three loop instructions per channel.
+// A workgroup of WAVES wavefronts shares each staged channel among its
+// WAVES * DW DMs.  Staging copies 16 bytes per lane per DMA instruction
+// (buffer_load_dwordx4 ... lds writes each lane's 16 bytes contiguously, and
+// its range check is per dword, so the last partial vector of a row keeps its
+// in-range samples and zero-fills the rest), four instructions per M0 value
+// through immediate offsets, and only the part of the row the tile's DMs read
+// at that channel (66 K samples plus the channel's shift span within the
+// tile, whole 64-sample pieces, never past the slot).  Each wave's channel
+// offset and span for the next stage are read a stage ahead.
 template <int DW, int K, int OCC_, int WAVES,
           void (*STEP)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned, unsigned*, int),
           int (*FAST)(float*, int2v*, unsigned, unsigned, const int32_t*, unsigned, unsigned*, int)>
@@ -349,22 +349,27 @@ struct BodyWinStage {
     const int lane = threadIdx.x & 63;
     const int wave = wave_id();
     const float* in = static_cast<const float*>(p.in);
-    const int slot = p.slot;  // multiple of 256 samples
+    const int slot = p.slot;  // multiple of 64 samples, at least 66K + every channel's span
     const int cc_max = p.cc;
     const int nstage = (p.nchans + cc_max - 1) / cc_max;
     const int row_bytes = static_cast<int>(p.nsamp * 4);
     const unsigned lane_addr = static_cast<unsigned>(reinterpret_cast<uintptr_t>(lds)) +
                                static_cast<unsigned>(lane * K * 4);
     const int32_t* basew = p.base + static_cast<int64_t>(dtile) * p.nchans;
-    const int slot_hi = slot & ~1023, rem = (slot >> 8) & 3;
-    // one channel row into LDS: whole groups of four 16-byte DMA instructions
-    // per M0 value, then the remaining one to three
-    auto dma_row = [&](const float* row, float* dst, int g0) {
+    const int32_t* spanw = p.aux + static_cast<int64_t>(dtile) * p.nchans;
+    // One channel row into LDS: only the samples this tile's DMs read at
+    // this channel (lane 63's window ends 66K samples plus the channel's
+    // span after the window start), in whole 64-sample pieces: groups of
+    // four 16-byte DMA instructions per M0 value, then up to three more,
+    // then up to three 4-byte ones.
+    auto dma_row = [&](const float* row, float* dst, int g0, int span) {
+      const int len = min(slot, (66 * K + span + 63) & ~63);
+      const int hi = len & ~1023, mid = (len >> 8) & 3, lo = (len >> 6) & 3;
       __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), 0, row_bytes, 0x00020000);
       const unsigned voff = static_cast<unsigned>(g0 + 4 * lane) * 4u;
 #pragma unroll 1
-      for (int e = 0; e < slot_hi; e += 1024) {
+      for (int e = 0; e < hi; e += 1024) {
         lds_void_t* d = (lds_void_t*)(dst + e);
         const unsigned v = voff + static_cast<unsigned>(e) * 4u;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 0, 0);
@@ -372,12 +377,20 @@ struct BodyWinStage {
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 2048, 0);
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 3072, 0);
       }
-      if (rem) {
-        lds_void_t* d = (lds_void_t*)(dst + slot_hi);
-        const unsigned v = voff + static_cast<unsigned>(slot_hi) * 4u;
+      if (mid) {
+        lds_void_t* d = (lds_void_t*)(dst + hi);
+        const unsigned v = voff + static_cast<unsigned>(hi) * 4u;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 0, 0);
-        if (rem > 1) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 1024, 0);
-        if (rem > 2) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 2048, 0);
+        if (mid > 1) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 1024, 0);
+        if (mid > 2) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, v, 0, 2048, 0);
+      }
+      if (lo) {
+        const int e = hi + 256 * mid;
+        lds_void_t* d = (lds_void_t*)(dst + e);
+        const unsigned v = static_cast<unsigned>(g0 + e + lane) * 4u;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, 0, 0, 0);
+        if (lo > 1) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, 0, 256, 0);
+        if (lo > 2) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, 0, 512, 0);
       }
     };
     // this wave's first channel of each stage, a stage ahead: its row, its
@@ -386,19 +399,26 @@ struct BodyWinStage {
     const int64_t rstep = static_cast<int64_t>(cc_max) * p.in_stride;
     float* dst0 = lds + wave * slot;
     float* dst1 = dst0 + cc_max * slot;
-    int gb_next = wave < min(cc_max, p.nchans) ? cload1(basew + wave) : 0;
+    int gb_next = 0, sp_next = 0;
+    if (wave < min(cc_max, p.nchans)) {
+      gb_next = cload1(basew + wave);
+      sp_next = cload1(spanw + wave);
+    }
     auto issue = [&](int s, int buf) {
       const int c0 = s * cc_max;
       const int ncc = min(cc_max, p.nchans - c0);
-      if (wave < ncc) dma_row(rowp, buf ? dst1 : dst0, static_cast<int>(t0) + gb_next);
+      if (wave < ncc) dma_row(rowp, buf ? dst1 : dst0, static_cast<int>(t0) + gb_next, sp_next);
       for (int i = wave + WAVES; i < ncc; i += WAVES) {  // more channels than wavefronts
         const int c = c0 + i;
         dma_row(in + static_cast<int64_t>(c) * p.in_stride, lds + (buf * cc_max + i) * slot,
-                static_cast<int>(t0) + cload1(basew + c));
+                static_cast<int>(t0) + cload1(basew + c), cload1(spanw + c));
       }
       rowp += rstep;
       const int cn = c0 + cc_max + wave;
-      if (cn < p.nchans && wave < cc_max) gb_next = cload1(basew + cn);
+      if (cn < p.nchans && wave < cc_max) {
+        gb_next = cload1(basew + cn);
+        sp_next = cload1(spanw + cn);
+      }
     };
     float acc[DW * K];
 #pragma unroll
@@ -438,7 +458,7 @@ struct BodyWinStage {
     }
   }
   static int geometry(int span_max, int cc_req, int* slot, int* cc, size_t* lds) {
-    const int s = (TT + span_max + WMAX + 255) & ~255;
+    const int s = (TT + span_max + WMAX + 63) & ~63;
     const size_t sb = static_cast<size_t>(s) * sizeof(float);
     // 4 * OCC wavefronts per CU share its 160 KB
     const size_t budget = static_cast<size_t>(160 * 1024) * WAVES / (4 * OCC);
@@ -2031,6 +2051,7 @@ dd_status prepare(const TileShape& s, dd_dtype in_t, const ExecArgs& a, Prepared
   } else if (impl.table_jump.dw) {
     st = plan_jumptab(a.plan, impl.td, impl.table_jump, &tab);
     if (st != DD_OK) return st;
+    aux = tt->d_span;  // the stage kernel stages each channel's own span only
   } else if (impl.table_win) {
     // window starts are below the slot, which geometry() has just bounded
     // below the schedule's 14 bits (static_assert in BodyWin)

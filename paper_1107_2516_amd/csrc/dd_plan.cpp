@@ -114,6 +114,7 @@ dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out) {
   // +8: kernels fetch a wavefront's entries with one 4- or 8-dword scalar load
   std::vector<int32_t> rel(static_cast<size_t>(ntiles) * nch * td + 8, 0);
   std::vector<int32_t> rows(static_cast<size_t>(ntiles) * td, -1);
+  std::vector<int32_t> span(static_cast<size_t>(ntiles) * nch, 0);
   TileTables tt;
   tt.td = td;
   tt.ntiles = ntiles;
@@ -134,6 +135,8 @@ dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out) {
         const int32_t r = plan->delays[static_cast<size_t>(src) * nch + c] - lo;
         rel[(static_cast<size_t>(tile) * nch + c) * td + j] = r;
         tt.span_tile[tile] = std::max(tt.span_tile[tile], static_cast<int>(r));
+        int32_t& sc = span[static_cast<size_t>(tile) * nch + c];
+        sc = std::max(sc, r);
       }
     }
     tt.span_max = std::max(tt.span_max, tt.span_tile[tile]);
@@ -141,16 +144,20 @@ dd_status plan_tiles(dd_plan* plan, int td, const TileTables** out) {
   hipError_t e = hipMalloc(&tt.d_base, base.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&tt.d_rel, rel.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&tt.d_rows, rows.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&tt.d_span, span.size() * sizeof(int32_t));
   if (e == hipSuccess)
     e = hipMemcpy(tt.d_base, base.data(), base.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(tt.d_rel, rel.data(), rel.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(tt.d_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(tt.d_span, span.data(), span.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(tt.d_base);
     (void)hipFree(tt.d_rel);
     (void)hipFree(tt.d_rows);
+    (void)hipFree(tt.d_span);
     return hip_error(e, "uploading tile tables");
   }
   auto res = dt.by_td.emplace(td, std::move(tt));
@@ -848,6 +855,7 @@ dd_plan::~dd_plan() {
       (void)hipFree(t.second.d_base);
       (void)hipFree(t.second.d_rel);
       (void)hipFree(t.second.d_rows);
+      (void)hipFree(t.second.d_span);
     }
     for (auto& t : kv.second.aoff) (void)hipFree(t.second);
     for (auto& t : kv.second.ralign) (void)hipFree(t.second);
