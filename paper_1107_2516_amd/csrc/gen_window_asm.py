@@ -553,6 +553,17 @@ def gen_stage(name, dw, k, occ, fast=False):
         out.append(f'      "s_mov_b32 s{TTG + 1}, s{TPC + 1}\\n"')
     for i in range(dw):
         out.append(f'      "s_mov_b64 s[{SA + 2 * i}:{SA + 2 * i + 1}], %[e{i}]\\n"')
+
+    def window_load(start_reg):
+        # DM 0's window (it always reloads), read ahead of its block: 3K/4
+        # ds_read_b128 from the window start (samples) * 4 + the LDS address
+        w = [f'      "v_lshl_add_u32 %[va], s{start_reg}, 2, %[addr]\\n"']
+        for i in range(3 * k // 4):
+            off = f" offset:{16 * i}" if i else ""
+            w.append(f'      "ds_read_b128 v[{va + 4 * i}:{va + 4 * i + 3}], %[va]{off}\\n"')
+        return w
+
+    out += window_load(SA + dw)
     out.append('      ".Lchan%=:\\n"')
     out.append(f'      "s_add_u32 s{TTG}, s{TPC}, s{SA}\\n"')
     if not fast:
@@ -599,30 +610,44 @@ def gen_stage(name, dw, k, occ, fast=False):
     for j in range(dw):
         for q in range(4):
             out += place(f".Lr%=_{j}_{q}", base + (j * 4 + q) * rbs)
+            if j == 0:
+                # the window was issued before the jump here (stage entry or
+                # the previous channel's tail): wait for it, then fetch the
+                # next channel's entries
+                out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+                out.append(f'      "{nload} s[{SB}:{SB + nb - 1}], %[tp], %[toff]\\n"')
+                for i in range(k):
+                    out.append(add(j, i, q + i)[0])
+                out += tail(j)
+                used = 4 + 8 + 4 * k + 12
+                assert (rbs - used) % 4 == 0 and used <= rbs
+                out += ['      "s_nop 0\\n"'] * ((rbs - used) // 4)  # never executed
+                continue
             # window start (samples) * 4 + the channel's LDS address: 8 B
             out.append(f'      "v_lshl_add_u32 %[va], s{SA + dw + j}, 2, %[addr]\\n"')
             for i in range(3 * k // 4):
                 off = f" offset:{16 * i}" if i else ""
                 out.append(f'      "ds_read_b128 v[{va + 4 * i}:{va + 4 * i + 3}], %[va]{off}\\n"')
             out.append('      "s_waitcnt lgkmcnt(0)\\n"')
-            if j == 0:
-                out.append(f'      "{nload} s[{SB}:{SB + nb - 1}], %[tp], %[toff]\\n"')
-            else:
-                out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
+            out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
             # q + i < K + 3 <= 3K: own registers only
             for i in range(k):
                 out.append(add(j, i, q + i)[0])
             out += tail(j)
     out.append('      ".Lnext%=:\\n"')
     out.append('      "s_waitcnt lgkmcnt(0)\\n"')
-    for i in range(dw):
-        out.append(f'      "s_mov_b64 s[{SA + 2 * i}:{SA + 2 * i + 1}], s[{SB + 2 * i}:{SB + 2 * i + 1}]\\n"')
     out.append('      "v_add_u32_e32 %[addr], %[ls], %[addr]\\n"')
     out.append('      "s_add_u32 %[toff], %[toff], %[ts]\\n"')
     out.append('      "s_sub_u32 %[cnt], %[cnt], 1\\n"')
-    out.append('      "s_cbranch_scc0 .Lchan%=\\n"')
+    out.append('      "s_cbranch_scc1 .Llast%=\\n"')
+    # another channel: its DM 0 window goes out first, then the hand-over
+    out += window_load(SB + dw)
     for i in range(dw):
-        out.append(f'      "s_mov_b64 %[e{i}], s[{SA + 2 * i}:{SA + 2 * i + 1}]\\n"')
+        out.append(f'      "s_mov_b64 s[{SA + 2 * i}:{SA + 2 * i + 1}], s[{SB + 2 * i}:{SB + 2 * i + 1}]\\n"')
+    out.append('      "s_branch .Lchan%=\\n"')
+    out.append('      ".Llast%=:\\n"')
+    for i in range(dw):
+        out.append(f'      "s_mov_b64 %[e{i}], s[{SB + 2 * i}:{SB + 2 * i + 1}]\\n"')
     if fast:
         out.append('      ".Lout%=:\\n"')
     outs = []
