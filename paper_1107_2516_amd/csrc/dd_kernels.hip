@@ -1674,37 +1674,45 @@ __global__ __launch_bounds__(ThreadsOf<Body>::value, BatchOcc<Body>::value) void
                                                          int32_t nbeams, int32_t total,
                                                          unsigned* __restrict__ counters) {
   (void)total;
-  __shared__ int s_item, s_beam;
+  __shared__ int s_item, s_part;
   const int xcd = blockIdx.x & 7;
   while (true) {
     if (threadIdx.x == 0) {
-      int item = -1, beam = 0;
+      int item = -1, part = 0;
       for (int k = 0; k < 8 && item < 0; k++) {
         const int x = (xcd + k) & 7;
-        const int32_t* f = first8 + x * (nbeams + 1);
-        const int hi = f[nbeams];
+        const int hi = first8[x * (nbeams + 1) + nbeams];
         if (hi <= 0) continue;
         const unsigned i = atomicAdd(&counters[x], 1u);
         if (i < static_cast<unsigned>(hi)) {
-          const int j = static_cast<int>(i);
-          while (beam + 1 < nbeams && f[beam + 1] <= j) beam++;
-          // the item's index within its beam: the start of the beam's
-          // eighth x plus its rank within that eighth
-          item = static_cast<int>((static_cast<int64_t>(beams[beam].nblocks) * x) / 8) +
-                 (j - f[beam]);
+          item = static_cast<int>(i);
+          part = x;
         }
       }
       s_item = item;
-      s_beam = beam;
+      s_part = part;
     }
     __syncthreads();
     // wave-uniform by construction; readfirstlane lets the compiler keep the
-    // beam's parameters in SGPRs
-    const int local = __builtin_amdgcn_readfirstlane(s_item);
-    const int beam = __builtin_amdgcn_readfirstlane(s_beam);
-    __syncthreads();  // s_item / s_beam are rewritten on the next pass
-    if (local < 0) break;
-    const KParams p = beams[beam];
+    // item, its beam and the beam's parameters in SGPRs
+    const int j = __builtin_amdgcn_readfirstlane(s_item);
+    const int x = __builtin_amdgcn_readfirstlane(s_part);
+    __syncthreads();  // s_item / s_part are rewritten on the next pass
+    if (j < 0) break;
+    // the item's beam: the last b with first8[x][b] <= j (beams with no
+    // items in this eighth share their successor's entry, so the search
+    // never stops on one), by binary search through scalar loads
+    const int32_t* f = first8 + x * (nbeams + 1);
+    int lo = 0, hi = nbeams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cload1(f + mid) <= j) lo = mid;
+      else hi = mid - 1;
+    }
+    const KParams p = beams[lo];
+    // its index within the beam: the start of the beam's eighth x plus its
+    // rank within that eighth
+    const int local = static_cast<int>((static_cast<int64_t>(p.nblocks) * x) / 8) + (j - cload1(f + lo));
     Body::run(p, local % p.n_dtiles, local / p.n_dtiles);
     __syncthreads();  // LDS is reused by the next item
   }
