@@ -460,10 +460,13 @@ def shared_layout(dw, k):
                          3K <= o+i: DPP from the next lane, 8 B), then the jump
                          to DM j+1's block (12 B), padded with s_nop to the
                          largest block (8K + 12 B)
-    reload block (j, q): v_lshl_add_u32 (8 B), 3K/4 ds_read_b128 (8 B each),
-                         s_waitcnt, the scalar load of the next channel's
-                         entries on DM 0 (8 B) or two s_nop, K adds of
-                         registers q..q+K-1 (4 B each) and the jump"""
+    reload block (j, q): v_lshl_add_u32 (8 B), 3K/4 ds_read_b128 (8 B each)
+                         (DM 0's are issued before its block, so its block
+                         starts at the next item), a partial s_waitcnt, K adds
+                         of registers q..q+K-1 (4 B each), s_waitcnt for the
+                         whole window, on DM 0 the scalar load of the next
+                         channel's entries (8 B), and the jump; padded with
+                         never-executed s_nop to the largest"""
     np_ = 3 * k + 1
     pbs = 8 * k + 12
     rbs = 8 + 8 * (3 * k // 4) + 4 + 8 + 4 * k + 12
@@ -610,16 +613,25 @@ def gen_stage(name, dw, k, occ, fast=False):
     for j in range(dw):
         for q in range(4):
             out += place(f".Lr%=_{j}_{q}", base + (j * 4 + q) * rbs)
+            # The block's own adds read registers q..q+K-1 (q + i < K + 3 <=
+            # 3K: own registers only), which the first K/4 + 1 of the 3K/4
+            # window reads fill; LDS reads complete in order, so once at most
+            # K/2 - 1 LDS/scalar operations are outstanding those have landed
+            # (an older scalar load still in flight only means more have).
+            # The rest of the window, which the later DMs' blocks read, is
+            # waited for after the adds.
+            early = f'      "s_waitcnt lgkmcnt({k // 2 - 1})\\n"'
             if j == 0:
                 # the window was issued before the jump here (stage entry or
-                # the previous channel's tail): wait for it, then fetch the
-                # next channel's entries
-                out.append('      "s_waitcnt lgkmcnt(0)\\n"')
-                out.append(f'      "{nload} s[{SB}:{SB + nb - 1}], %[tp], %[toff]\\n"')
+                # the previous channel's tail): wait for its first reads, add,
+                # wait for the rest, then fetch the next channel's entries
+                out.append(early)
                 for i in range(k):
                     out.append(add(j, i, q + i)[0])
+                out.append('      "s_waitcnt lgkmcnt(0)\\n"')
+                out.append(f'      "{nload} s[{SB}:{SB + nb - 1}], %[tp], %[toff]\\n"')
                 out += tail(j)
-                used = 4 + 8 + 4 * k + 12
+                used = 4 + 4 * k + 4 + 8 + 12
                 assert (rbs - used) % 4 == 0 and used <= rbs
                 out += ['      "s_nop 0\\n"'] * ((rbs - used) // 4)  # never executed
                 continue
@@ -628,12 +640,14 @@ def gen_stage(name, dw, k, occ, fast=False):
             for i in range(3 * k // 4):
                 off = f" offset:{16 * i}" if i else ""
                 out.append(f'      "ds_read_b128 v[{va + 4 * i}:{va + 4 * i + 3}], %[va]{off}\\n"')
-            out.append('      "s_waitcnt lgkmcnt(0)\\n"')
-            out += ['      "s_nop 0\\n"', '      "s_nop 0\\n"']
-            # q + i < K + 3 <= 3K: own registers only
+            out.append(early)
             for i in range(k):
                 out.append(add(j, i, q + i)[0])
+            out.append('      "s_waitcnt lgkmcnt(0)\\n"')
             out += tail(j)
+            used = 8 + 8 * (3 * k // 4) + 4 + 4 * k + 4 + 12
+            assert (rbs - used) % 4 == 0 and used <= rbs
+            out += ['      "s_nop 0\\n"'] * ((rbs - used) // 4)  # never executed
     out.append('      ".Lnext%=:\\n"')
     out.append('      "s_waitcnt lgkmcnt(0)\\n"')
     out.append('      "v_add_u32_e32 %[addr], %[ls], %[addr]\\n"')
