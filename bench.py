@@ -845,6 +845,15 @@ def run_serve(dd, torch, args, nbeams=64):
     kernel_rate = plan.ndms * max_chunk / (kms * 1e-3)
     adds = float(plan.ndms) * plan.nchans * max_chunk
 
+    # the plain kernel over the saturating phase's own chunks (carry + each
+    # chunk length, in the same order) back to back on one stream: the same
+    # kernel work with none of the serving machinery around it
+    def same_chunks():
+        for n in lens:
+            plan.execute(xk[:, :m + n], out=ok[:, :n])
+    mix_ms, _ = timed(stream, same_chunks, 1, 1)
+    mix_rate = sat_samples * plan.ndms / (mix_ms * 1e-3)
+
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle on one beam's carry + largest chunk (a sample of DM rows),
@@ -891,6 +900,8 @@ def run_serve(dd, torch, args, nbeams=64):
                                                        plan.ndms * max_chunk * 4.0, kms,
                                                        "TOP/s")},
         "served_over_kernel": (sat_samples * plan.ndms / sat_wall) / kernel_rate,
+        "kernel_same_chunks": {"chunks": len(lens), "kernel_ms": mix_ms, "value": mix_rate},
+        "served_over_kernel_same_chunks": (sat_samples * plan.ndms / sat_wall) / mix_rate,
     }
 
 
