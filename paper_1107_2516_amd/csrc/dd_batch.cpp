@@ -96,7 +96,7 @@ dd_status configure(dd_batch* b, const std::vector<TileShape>& shapes, const Til
     DD_HIP(hipMalloc(&b->d_first, 8 * (b->items.size() + kMaxBatchParts) * sizeof(int32_t)));
     for (auto& sl : b->slot) {
       DD_HIP(hipMalloc(&sl.d_params, bl.params.size()));
-      DD_HIP(hipMalloc(&sl.d_counters, 64 * sizeof(unsigned)));
+      DD_HIP(hipMalloc(&sl.d_counters, 8 * kMaxBatchParts * sizeof(unsigned)));
       DD_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
     }
   }

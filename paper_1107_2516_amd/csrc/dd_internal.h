@@ -272,7 +272,7 @@ dd_status launch_dedisperse(const TileShape& shape, dd_dtype in_t, const ExecArg
 
 // One class of a batch: the beams that run the same kernel, as one
 // persistent launch.
-constexpr size_t kMaxBatchParts = 8;  // work counters: 8 per part, 64 in all
+constexpr size_t kMaxBatchParts = 16;  // work counters: 8 per part, 128 in all
 struct BatchPart {
   const void* kernel = nullptr;
   int grid = 0;           // persistent grid: CUs x resident workgroups per CU

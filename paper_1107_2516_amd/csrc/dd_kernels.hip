@@ -2226,22 +2226,51 @@ dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* 
                         BatchLaunch* out) {
   // Beam i prepared with its shape (mapped to one with a persistent form);
   // beams whose tables do not suit that shape's kernel get the kernel they
-  // fall back to.  Beams are grouped by kernel into classes, one persistent
-  // launch per class, launched one after the other.
+  // fall back to.  Beams are grouped into classes by kernel and by the
+  // workgroups per CU their own LDS allows (a class's launch gives every
+  // workgroup the LDS of its largest beam, so one class per occupancy keeps
+  // small-LDS beams from running at a large beam's occupancy); one
+  // persistent launch per class, launched one after the other.  With more
+  // classes than launches, beams are grouped by kernel alone.
   std::vector<PreparedLaunch> pls(static_cast<size_t>(n));
-  std::vector<const void*> kinds;
-  std::vector<int> kind_of(static_cast<size_t>(n));
+  std::vector<const void*> kernels;
+  std::vector<size_t> kernel_lds;
   for (int i = 0; i < n; i++) {
     dd_status st = prepare(batch_shape(shapes[i], in_t), in_t, beams[i], &pls[i]);
     if (st != DD_OK) return st;
-    auto it = std::find(kinds.begin(), kinds.end(), pls[i].impl.batch);
-    if (it == kinds.end()) {
-      if (kinds.size() == kMaxBatchParts)
-        return set_error(DD_ERR_TOO_LARGE, "beams need too many different kernels");
-      kinds.push_back(pls[i].impl.batch);
-      it = kinds.end() - 1;
+    auto it = std::find(kernels.begin(), kernels.end(), pls[i].impl.batch);
+    if (it == kernels.end()) {
+      kernels.push_back(pls[i].impl.batch);
+      kernel_lds.push_back(0);
+      it = kernels.end() - 1;
     }
-    kind_of[i] = static_cast<int>(it - kinds.begin());
+    size_t& m = kernel_lds[static_cast<size_t>(it - kernels.begin())];
+    m = std::max(m, pls[i].lds);
+  }
+  if (kernels.size() > kMaxBatchParts)
+    return set_error(DD_ERR_TOO_LARGE, "beams need too many different kernels");
+  for (size_t k = 0; k < kernels.size(); k++) {
+    dd_status st = set_lds_limit(kernels[k], kernel_lds[k]);
+    if (st != DD_OK) return st;
+  }
+  std::vector<std::pair<const void*, int>> kinds;
+  std::vector<int> kind_of(static_cast<size_t>(n));
+  for (int pass = 0; pass < 2; pass++) {
+    kinds.clear();
+    for (int i = 0; i < n; i++) {
+      int per_cu = 0;
+      if (pass == 0)
+        DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pls[i].impl.batch,
+                                                            pls[i].impl.threads, pls[i].lds));
+      const std::pair<const void*, int> key(pls[i].impl.batch, per_cu);
+      auto it = std::find(kinds.begin(), kinds.end(), key);
+      if (it == kinds.end()) {
+        kinds.push_back(key);
+        it = kinds.end() - 1;
+      }
+      kind_of[i] = static_cast<int>(it - kinds.begin());
+    }
+    if (kinds.size() <= kMaxBatchParts) break;
   }
   out->params.assign(static_cast<size_t>(n) * sizeof(KParams), 0);
   out->first_item.assign(8 * (static_cast<size_t>(n) + kinds.size()), 0);
@@ -2281,11 +2310,9 @@ dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* 
       if (acc > INT32_MAX / 2) return set_error(DD_ERR_TOO_LARGE, "too many work items");
     }
     pfirst += 8 * (static_cast<size_t>(nb) + 1);
-    part.kernel = kinds[k];
+    part.kernel = kinds[k].first;
     part.nbeams = nb;
     part.total = static_cast<int32_t>(total);
-    dd_status st = set_lds_limit(part.kernel, part.lds);
-    if (st != DD_OK) return st;
     int per_cu = 0;
     DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, part.kernel, part.threads,
                                                         part.lds));

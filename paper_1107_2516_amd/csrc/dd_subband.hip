@@ -97,8 +97,11 @@ size_t param_area(int n) {
          round256(8 * (static_cast<size_t>(n) + dd::kMaxBatchParts) * 4);
 }
 
+// the persistent kernels' work counters: 8 per kernel class
+size_t counters_area() { return round256(8 * dd::kMaxBatchParts * sizeof(unsigned)); }
+
 size_t params_workspace(const dd_subband_plan* sp) {
-  size_t b = 256;  // the work counters
+  size_t b = counters_area();
   for (const dd::Pass& ps : sp->passes) b += param_area(sp->nsub) + param_area(stage2_items(ps));
   return b;
 }
@@ -274,7 +277,7 @@ dd_status dd_subband_execute(const dd_subband_plan* csp, const float* d_in, int6
       size_t off = 0;  // parameter array offset from pbase; prefix sums follow
     };
     std::vector<Stage> stages;
-    const size_t host_bytes = params_workspace(sp) - 256;
+    const size_t host_bytes = params_workspace(sp) - counters_area();
     int dev = 0;
     DD_HIP(hipGetDevice(&dev));
     if (sp->copied) {
