@@ -94,6 +94,16 @@ __device__ __forceinline__ const cint32_t* const_ptr(const int32_t* p) {
   return (const cint32_t*)uniform_ptr(p);
 }
 __device__ __forceinline__ int cload1(const int32_t* p) { return *const_ptr(p); }
+// Outputs and row maps through the global address space: a pointer read from
+// a parameter block in memory (the persistent kernel's beams) is generic to
+// the compiler, which would then use flat instructions, and those also count
+// against the LDS wait counter.
+template <class T>
+using gptr_t = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr_t<T> gptr(const void* p) {
+  return (gptr_t<T>)p;
+}
 template <int DW>
 __device__ __forceinline__ void cload_dw(const int32_t* p, int* r) {
   const cint32_t* q = const_ptr(p);
@@ -166,10 +176,10 @@ struct BodyLds {
         }
       }
     }
-    Tout* out = static_cast<Tout*>(p.out);
+    gptr_t<Tout> out = gptr<Tout>(p.out);
 #pragma unroll
     for (int d = 0; d < DW; d++) {
-      const int row = p.rows[dtile * TD + wave * DW + d];
+      const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + d];
       if (row < 0) continue;
 #pragma unroll
       for (int k = 0; k < K; k++) {
@@ -277,12 +287,12 @@ struct BodyWin {
         for (int j = 0; j < DW * EW; j++) r[j] = rn[j];
       }
     }
-    float* out = static_cast<float*>(p.out);
+    gptr_t<float> out = gptr<float>(p.out);
 #pragma unroll
     for (int j = 0; j < DW; j++) {
-      const int row = p.rows[dtile * TD + wave * DW + j];
+      const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
       if (row < 0) continue;
-      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+      gptr_t<float> o = out + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
       for (int k = 0; k < K; k++) {
         const int64_t t = t0 + lane * K + k;
@@ -444,12 +454,12 @@ struct BodyWinStage {
       if (!FAST(acc, e, a, static_cast<unsigned>(slot * 4), tabw, TD * 8, &toff, ncc - 1))
         STEP(acc, e, a, static_cast<unsigned>(slot * 4), tabw, TD * 8, &toff, ncc - 1);
     }
-    float* out = static_cast<float*>(p.out);
+    gptr_t<float> out = gptr<float>(p.out);
 #pragma unroll
     for (int j = 0; j < DW; j++) {
-      const int row = p.rows[dtile * TD + wave * DW + j];
+      const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
       if (row < 0) continue;
-      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+      gptr_t<float> o = out + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
       for (int k = 0; k < K; k++) {
         const int64_t t = t0 + lane * K + k;
@@ -649,12 +659,12 @@ struct BodyPairs {
         for (int j = 0; j < kPairEntryWords; j++) e[j] = en[j];
       }
     }
-    float* out = static_cast<float*>(p.out);
+    gptr_t<float> out = gptr<float>(p.out);
 #pragma unroll
     for (int j = 0; j < DW; j++) {
-      const int row = p.rows[dtile * TD + wave * DW + j];
+      const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
       if (row < 0) continue;
-      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+      gptr_t<float> o = out + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
       for (int k = 0; k < K; k++) {
         const int64_t t = t0 + lane * K + k;
@@ -844,9 +854,9 @@ struct BodyPairsU8 {
     auto flush = [&]() {
 #pragma unroll
       for (int j = 0; j < DW; j++) {
-        const int row = p.rows[dtile * TD + wave * DW + j];
+        const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
         if (row >= 0) {
-          int32_t* o = static_cast<int32_t*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+          gptr_t<int32_t> o = gptr<int32_t>(p.out) + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
           for (int i = 0; i < IDW; i++) {
             const int64_t tb = t0 + 2 * static_cast<int64_t>(lane + 64 * i);
@@ -1056,12 +1066,12 @@ struct BodyPairsF16 {
         }
       }
     }
-    float* out = static_cast<float*>(p.out);
+    gptr_t<float> out = gptr<float>(p.out);
 #pragma unroll
     for (int j = 0; j < DW; j++) {
-      const int row = p.rows[dtile * TD + wave * DW + j];
+      const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
       if (row < 0) continue;
-      float* o = out + static_cast<int64_t>(row) * p.out_stride;
+      gptr_t<float> o = out + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
       for (int i = 0; i < I; i++) {
         const int64_t t = t0 + lane + 64 * i;
@@ -1218,9 +1228,9 @@ struct BodyCopies {
       if constexpr (EPD == 4) {
 #pragma unroll
         for (int j = 0; j < DW; j++) {
-          const int row = p.rows[dtile * TD + wave * DW + j];
+          const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
           if (row >= 0) {
-            int32_t* o = static_cast<int32_t*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+            gptr_t<int32_t> o = gptr<int32_t>(p.out) + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
             for (int ii = 0; ii < I; ii++) {
               const int64_t tb = t0 + 4 * static_cast<int64_t>(lane + 64 * ii);
@@ -1362,9 +1372,9 @@ struct BodyCopies {
     } else {
 #pragma unroll
       for (int j = 0; j < DW; j++) {
-        const int row = p.rows[dtile * TD + wave * DW + j];
+        const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
         if (row < 0) continue;
-        float* o = static_cast<float*>(p.out) + static_cast<int64_t>(row) * p.out_stride;
+        gptr_t<float> o = gptr<float>(p.out) + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
         for (int ii = 0; ii < I; ii++) {
           const int64_t tb = t0 + static_cast<int64_t>(EPD) * (lane + 64 * ii);
@@ -1513,12 +1523,12 @@ struct BodyWinX {
     // u8: move the 16-bit lane sums into the int32 output and clear them
     auto flush = [&](bool first) {
       if constexpr (U8) {
-        int32_t* out = static_cast<int32_t*>(p.out);
+        gptr_t<int32_t> out = gptr<int32_t>(p.out);
 #pragma unroll
         for (int j = 0; j < DW; j++) {
-          const int row = p.rows[dtile * TD + wave * DW + j];
+          const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
           if (row >= 0) {
-            int32_t* o = out + static_cast<int64_t>(row) * p.out_stride;
+            gptr_t<int32_t> o = out + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
             for (int i = 0; i < K / 2; i++) {
               const uint32_t a = acc[j * (K / 2) + i];
@@ -1570,12 +1580,12 @@ struct BodyWinX {
     if constexpr (U8) {
       if (since || first) flush(first);
     } else {
-      float* out = static_cast<float*>(p.out);
+      gptr_t<float> out = gptr<float>(p.out);
 #pragma unroll
       for (int j = 0; j < DW; j++) {
-        const int row = p.rows[dtile * TD + wave * DW + j];
+        const int row = gptr<const int32_t>(p.rows)[dtile * TD + wave * DW + j];
         if (row < 0) continue;
-        float* o = out + static_cast<int64_t>(row) * p.out_stride;
+        gptr_t<float> o = out + static_cast<int64_t>(row) * p.out_stride;
 #pragma unroll
         for (int k = 0; k < K; k++) {
           const int64_t t = tb + k;
