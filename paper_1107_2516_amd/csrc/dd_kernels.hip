@@ -2344,8 +2344,8 @@ dd_status batch_prepare(const TileShape* shapes, dd_dtype in_t, const ExecArgs* 
 size_t batch_param_size() { return sizeof(KParams); }
 
 dd_status batch_zero_counters(const BatchLaunch& b, unsigned* d_counters, hipStream_t stream) {
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, d_counters,
-                     8 * static_cast<int>(b.parts.size()));
+  const int n = 8 * static_cast<int>(b.parts.size());  // up to 8 * kMaxBatchParts
+  hipLaunchKernelGGL(k_zero, dim3((n + 63) / 64), dim3(64), 0, stream, d_counters, n);
   DD_HIP(hipGetLastError());
   return DD_OK;
 }
