@@ -161,10 +161,13 @@ typedef struct dd_batch_item {
  * persistent kernels: every (beam, DM tile, time tile) work item is pulled
  * from a device queue by a fixed grid sized to the GPU, each XCD taking an
  * eighth of every beam first.  Each beam's tile shape comes from the
- * autotune cache (dd_autotune) or the built-in defaults; beams whose shapes
- * run different kernels form classes, one persistent kernel per class, run
- * one after the other (at most 8 classes, else DD_ERR_TOO_LARGE).  The launch
- * is recorded into a HIP graph on first use and replayed afterwards.
+ * autotune cache (dd_autotune) or the built-in defaults.  Beams are grouped
+ * into classes by the kernel their shape runs and by the workgroups per CU
+ * their own LDS needs allow (a class's workgroups all get the LDS of its
+ * largest beam); one persistent kernel per class, run one after the other.
+ * At most 16 classes: beyond that, beams are grouped by kernel alone, and
+ * more than 16 different kernels give DD_ERR_TOO_LARGE.  The launch is
+ * recorded into a HIP graph on first use and replayed afterwards.
  */
 dd_status dd_batch_create(const dd_batch_item* items, int32_t n, dd_dtype in_t, dd_dtype out_t,
                           dd_batch** out);
